@@ -1,0 +1,200 @@
+/*
+ * pk.h -- parametric matmul kernels for gfx950 (MI355X), C ABI.
+ *
+ * A parametric kernel keeps its program parameters (thread-block shape,
+ * per-thread coarsening, LDS tile extents) symbolic when it is generated and
+ * learns the machine parameters only when it is loaded (Section 1; Section 2,
+ * Fig. 4).  A comprehensive parametric kernel is a case discussion: a list of
+ * leaves (C_i, S_i) where C_i is a conjunction of polynomial constraints on
+ * machine and program parameters and S_i the program optimized under C_i
+ * (Definition 3), produced by Algorithms 1 and 2 (Section 3).
+ *
+ * This library holds
+ *   - the symbolic engine of Algorithms 1 and 2 (pk_co_solve),
+ *   - the case tables of its matmul kernel families, built once per process
+ *     and bound to the machine parameters read from hipDeviceProp_t
+ *     (pk_case_table_build),
+ *   - load-time selection of a leaf and its program parameters (pk_select),
+ *   - the hand-written HIP kernels of every leaf (pk_matmul, and
+ *     pk_matmul_batched for many independent products in one launch).
+ *
+ * Conventions shared by every entry point:
+ *   - return value: PK_OK (0) or a negative PK_ERR_* code; nothing throws
+ *     across this boundary; pk_last_error() gives a thread-local message;
+ *   - matrices are row-major: element (i, j) of X is X[i * ldx + j];
+ *   - device pointers are HIP device addresses owned by the caller, which must
+ *     keep them alive until the work queued on the given stream completes;
+ *   - hip_stream is a hipStream_t (NULL = the default stream); matmul calls
+ *     are asynchronous on it.
+ */
+#ifndef PK_H
+#define PK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define PK_OK 0
+#define PK_ERR_INVALID_ARG -1         /* null pointer, negative size, ld too small, misaligned */
+#define PK_ERR_NO_FEASIBLE_BRANCH -2  /* no leaf of the case table holds (refuse with no strategy left) */
+#define PK_ERR_UNSUPPORTED_DTYPE -3   /* the dtype has no kernel in the requested family */
+#define PK_ERR_NOT_INSTANTIATED -4    /* parameters satisfy the constraints but no compiled instance exists */
+#define PK_ERR_HIP -5                 /* a HIP runtime call failed; the message holds its code */
+#define PK_ERR_COST_MODEL -6          /* no usable cost model (selection fell back, or training failed) */
+#define PK_ERR_BUFFER_TOO_SMALL -7    /* an output buffer is too small; *needed holds the size */
+#define PK_ERR_PARSE -8               /* a family description given as text could not be parsed */
+
+/* Thread-local message describing the last error returned on this thread. */
+const char *pk_last_error(void);
+
+/* ------------------------------------------------------------------ types */
+typedef enum {
+    PK_F32 = 0,  /* float32 inputs, float32 output, float32 accumulation */
+    PK_I32 = 1,  /* int32 inputs and output, arithmetic modulo 2^32 */
+    PK_BF16 = 2  /* bfloat16 inputs (raw 16-bit patterns), float32 output and accumulation */
+} pk_dtype;
+
+/* Machine parameters (Section 3.2: the resource limits R_i), read from
+ * hipDeviceProp_t at load time or given by a caller to model another device. */
+typedef struct {
+    int32_t wave;              /* W: wavefront width (warpSize) */
+    int64_t lds_block;         /* Z: LDS bytes one workgroup may allocate (sharedMemPerBlock) */
+    int64_t lds_cu;            /* LDS bytes per compute unit (maxSharedMemoryPerMultiProcessor) */
+    int64_t regs_block;        /* V: 32-bit registers one workgroup may allocate (regsPerBlock) */
+    int64_t regs_cu;           /* registers per compute unit (regsPerMultiprocessor) */
+    int32_t max_threads_block; /* T: work-items per workgroup (maxThreadsPerBlock) */
+    int32_t max_threads_cu;    /* resident work-items per compute unit */
+    int32_t max_blocks_cu;     /* resident workgroups per compute unit */
+    int32_t cu_count;          /* NCU: compute units (multiProcessorCount) */
+    int32_t clock_khz;         /* shader clock (clockRate) */
+    char arch[64];             /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+} pk_machine;
+
+/* Kernel families, i.e. the code fragments S the comprehensive optimization
+ * is run on. */
+#define PK_FAMILY_VALU 0  /* the blocked kernel of Section 2 (Fig. 3, Fig. 4), f32 and i32 */
+#define PK_FAMILY_MFMA 1  /* LDS-tiled matrix-core kernel, f32 and bf16 */
+#define PK_NUM_FAMILIES 2
+
+/* Strategy bits of the VALU family (a variant is the set of strategies applied):
+ * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
+ * PK_VALU_NOLDS - operands read straight from global memory, no LDS (decision (4b)) */
+#define PK_VALU_GRAN 1
+#define PK_VALU_NOLDS 2
+/* Strategy bits of the MFMA family:
+ * PK_MFMA_SINGLE - one LDS stage instead of two (halves the LDS tile footprint) */
+#define PK_MFMA_SINGLE 1
+
+/* A leaf choice together with its program parameters E.
+ *   family  - PK_FAMILY_*
+ *   leaf    - leaf index in that family's table for the dtype, or -1
+ *   variant - strategy bits of the program to run, or -1
+ * VALU family: bx = threads along N (the paper's ub1), by = threads along M
+ *   (the paper's B0), s = outputs per thread along N (the paper's s), bk =
+ *   K extent of an LDS tile (the paper fixes it to B0; 0 means "= by").
+ * MFMA family: bm x bn output tile per workgroup, bk its K extent, wm x wn
+ *   wavefronts of 64 lanes; unused fields are 0. */
+typedef struct {
+    int32_t family;
+    int32_t leaf;
+    int32_t variant;
+    int32_t bx, by, s, bk;
+    int32_t bm, bn, wm, wn;
+} pk_params;
+
+/* Selection policies for pk_select. */
+#define PK_POLICY_CASE 0        /* first satisfied leaf per E, best analytic score over E */
+#define PK_POLICY_LEARNED 1     /* cost-model prediction over the feasible set */
+#define PK_POLICY_EXHAUSTIVE 2  /* time every feasible (leaf, E) on the device, keep the fastest */
+
+typedef struct pk_table pk_table; /* opaque; immutable once built */
+
+/* ------------------------------------------------------------------ machine */
+/* Fills *out from hipGetDeviceProperties(device).  Errors: PK_ERR_HIP. */
+int pk_machine_query(int device, pk_machine *out);
+
+/* ------------------------------------------------------------------ symbolic engine */
+/* Runs Algorithms 1 and 2 (Section 3.7) on a code fragment described in text
+ * and writes the leaves as JSON into out (cap bytes, NUL-terminated).
+ * The description lists symbols, finite domains, counters with their values
+ * after given strategy sets, and strategies with sigma (one item per line):
+ *     machine R T            program B0 B1          data N
+ *     domain R 0 40          (integer interval)     points B0 1 2 4 8 (list)
+ *     counter r_R resource R           value r_R gran : 10      value r_R : 14
+ *     strategy gran src r_R            (src | ir, then the counters of sigma)
+ *     perf_one 100                      (units of a performance measure's 1)
+ * A counter's value after a set of applied strategies is the first "value"
+ * line of that counter whose strategies are all applied.  Errors:
+ * PK_ERR_PARSE, PK_ERR_BUFFER_TOO_SMALL (*needed = bytes required). */
+int pk_co_solve(const char *spec, char *out, size_t cap, size_t *needed);
+
+/* ------------------------------------------------------------------ case table */
+/* Builds the comprehensive case tables of every family and dtype and binds
+ * them to the machine: the parameters of `device` (via pk_machine_query)
+ * when override_or_null is NULL, else the given descriptor (no GPU needed,
+ * then device is ignored).  The table is owned by the caller and freed with
+ * pk_case_table_free.  Errors: PK_ERR_HIP, PK_ERR_INVALID_ARG. */
+int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table **out);
+void pk_case_table_free(pk_table *tbl);
+
+/* JSON description of the table: the machine, every family's leaves (their
+ * strategy sets, lambda, constraint systems) and the compiled instances with
+ * their resource usage.  Errors: PK_ERR_BUFFER_TOO_SMALL (*needed). */
+int pk_case_table_describe(const pk_table *tbl, char *out, size_t cap, size_t *needed);
+
+/* Leaf lookup at fixed program parameters: *leaf_out = index of the first leaf
+ * of (family, dtype) whose system holds at the bound machine and at E given
+ * in *p (family, bx.. fields), and *variant_out its strategy bits.
+ * Errors: PK_ERR_NO_FEASIBLE_BRANCH (no leaf holds), PK_ERR_UNSUPPORTED_DTYPE,
+ * PK_ERR_INVALID_ARG (E outside the family's parameter domain). */
+int pk_case_table_lookup(const pk_table *tbl, pk_dtype dtype, const pk_params *p,
+                         int32_t *leaf_out, int32_t *variant_out);
+
+/* ------------------------------------------------------------------ selection */
+/* Chooses a leaf and program parameters for C(MxN) = A(MxK) B(KxN) under a
+ * policy and writes them to *out.  Every candidate satisfies its leaf's
+ * system at the bound machine.  PK_POLICY_EXHAUSTIVE launches kernels on the
+ * table's device on a private stream and synchronizes; its picks are cached
+ * per (dtype, M, N, K) for the table's lifetime.  PK_POLICY_LEARNED needs a
+ * model loaded with pk_costmodel_load (else PK_ERR_COST_MODEL and *out holds
+ * the CASE pick).  Errors: PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_INVALID_ARG. */
+int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int policy,
+              pk_params *out);
+
+/* ------------------------------------------------------------------ products */
+/* C = A B (accumulate = 0) or C = C + A B (accumulate = 1, the semantics of
+ * the kernel of Fig. 4, which loads c, adds the products and stores it back).
+ * A is MxK with leading dimension lda, B is KxN (ldb), C is MxN (ldc); for
+ * PK_BF16, A and B hold bfloat16 bit patterns and C is float32.
+ * params_or_null: NULL selects with PK_POLICY_CASE; otherwise
+ *   leaf >= 0           runs that leaf at E (its system must hold),
+ *   leaf < 0, variant>=0 runs that variant at E if its resources fit the machine
+ *                       (the "forced" mode used to test every program),
+ *   both < 0            looks the leaf up at E.
+ * M == 0 or N == 0 is a no-op; K == 0 writes zeros (or leaves C unchanged
+ * when accumulating).  Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
+ * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NOT_INSTANTIATED, PK_ERR_HIP. */
+int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype,
+              const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
+              int64_t M, int64_t N, int64_t K, int accumulate, void *hip_stream);
+
+/* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
+ * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */
+int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N,
+                    int64_t K, int64_t *grid, int32_t *block, int64_t *lds_bytes);
+
+/* Number of compiled kernel instances, and the name of instance i. */
+int pk_instance_count(void);
+const char *pk_instance_name(int i);
+
+/* Library version string. */
+const char *pk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PK_H */

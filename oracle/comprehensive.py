@@ -288,6 +288,10 @@ class Family:
     # the value that stands for 1 (100 %) in the units performance measures
     # and counters are given in, so that they stay integers
     perf_one: int = 1
+    # when given, the (program, data) parameter values range over this list
+    # of tuples (in the order program + data) instead of the product of the
+    # per-symbol domains
+    points: Optional[List[Tuple[int, ...]]] = None
 
     # performance measures are the machine symbols limiting performance counters
     def perf_symbols(self):
@@ -314,7 +318,12 @@ def consistent(system: Sequence[Constraint], fam: Family) -> bool:
         raise ValueError("symbols without a domain: %s" % sorted(unknown))
 
     # joint grid over program/data parameters
-    if grid_syms:
+    if fam.points is not None:
+        order = list(fam.program) + list(fam.data)
+        arr = np.asarray(fam.points, dtype=np.int64).reshape(len(fam.points), len(order))
+        env = {s: arr[:, k] for k, s in enumerate(order)}
+        npts = arr.shape[0]
+    elif grid_syms:
         axes = np.meshgrid(*[np.asarray(fam.domains[s], dtype=np.int64) for s in grid_syms], indexing="ij")
         env = {s: a.reshape(-1) for s, a in zip(grid_syms, axes)}
         npts = env[grid_syms[0]].size

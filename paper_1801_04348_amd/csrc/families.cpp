@@ -1,0 +1,241 @@
+// The matmul code fragments the comprehensive optimization runs on, with
+// their evaluation functions (Section 3.3) and strategies (Section 3.4).
+//
+// Machine parameters (Section 3.2), read from hipDeviceProp_t at load time:
+//   Z  LDS bytes a workgroup may allocate          (sharedMemPerBlock)
+//   V  32-bit registers a workgroup may allocate   (regsPerBlock)
+//   T  work-items per workgroup                    (maxThreadsPerBlock)
+// Resource counters, in gamma order (shared memory first, then registers, as
+// the counter order under which Algorithm 2 yields the systems printed for
+// Fig. 6 and Fig. 7), then threads:
+//   r_Z  LDS bytes of the workgroup: a polynomial in the program parameters,
+//        from the kernel's LDS layout
+//   r_V  registers of the workgroup: a table symbol per program (variant),
+//        the compiled instance's unified VGPR allocation times its lanes
+//   r_T  work-items of the workgroup
+//
+// VALU family (Section 2, Fig. 4 generalised), program parameters bx (threads
+// along N, the paper's ub1), by (threads along M, the paper's B0), s (outputs
+// per thread), K tile bk = by as in the paper.  Strategies, omega order:
+//   gran  (source; sigma = {r_Z, r_V}) one output per thread, decision (3b)
+//   nolds (source; sigma = {r_Z, r_V}) no LDS caching, decision (4b); the
+//         direct program also drops the LDS staging registers
+// The register-pressure strategy (1) of the experiments has no counterpart:
+// the compiler already fits each instance's registers to its launch bounds.
+//
+// MFMA family, program parameters bm, bn (output tile), bk (K tile), wm, wn
+// (wavefront grid).  Strategy:
+//   single (source; sigma = {r_Z, r_V}) one LDS stage instead of two (also no
+//          registers holding the next tile while the current one is used)
+#include <algorithm>
+#include <stdexcept>
+
+#include "pk_internal.hpp"
+
+namespace pk {
+
+namespace {
+
+struct MfmaPoint {
+    int bm, bn, bk, wm, wn;
+};
+
+// Program-parameter domains.  VALU: {4, 8, 16, 32}^2 x {1, 2, 4, 8}.
+const int kValuB[] = {4, 8, 16, 32};
+const int kValuS[] = {1, 2, 4, 8};
+
+const MfmaPoint kMfmaF32[] = {
+    {64, 64, 32, 2, 2},   {128, 64, 32, 2, 2},  {64, 128, 32, 2, 2},  {128, 128, 32, 2, 2},
+    {256, 128, 32, 4, 2}, {128, 256, 32, 2, 4}, {256, 256, 32, 4, 4},
+};
+const MfmaPoint kMfmaBf16[] = {
+    {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},  {128, 128, 64, 2, 2},
+    {256, 128, 64, 4, 2}, {128, 256, 64, 2, 4}, {256, 256, 64, 4, 4},
+};
+
+struct Syms {
+    int Z, V, T;
+};
+
+Syms add_machine(Family &f) {
+    for (const char *n : {"Z", "V", "T"}) {
+        f.sym_names.push_back(n);
+        f.sym_kind.push_back(SYM_MACHINE);
+        f.lo.push_back(0);
+        f.hi.push_back(INT64_MAX / 4);
+    }
+    return Syms{0, 1, 2};
+}
+
+int add_sym(Family &f, const char *name, int kind) {
+    f.sym_names.push_back(name);
+    f.sym_kind.push_back(kind);
+    f.lo.push_back(0);
+    f.hi.push_back(INT64_MAX / 4);
+    return (int)f.sym_names.size() - 1;
+}
+
+Poly P(int64_t c) { return Poly::constant(c); }
+Poly S(int id) { return Poly::symbol(id); }
+
+int64_t table_regs(int family, int variant, int dtype, const std::vector<int64_t> &pt, int wave) {
+    const KernelEntry *e = find_instance(family, variant, dtype, pt);
+    if (!e) return missing_table_value;
+    const KernelResources *r = resources_of(e->name);
+    if (!r) return missing_table_value;
+    return regs_per_block(*r, e->threads, wave);
+}
+
+}  // namespace
+
+// gfx950: per-lane allocation = align(align(VGPRs, 4) + AGPRs, 8); a
+// workgroup occupies whole wavefronts.
+int64_t regs_per_block(const KernelResources &r, int threads, int wave) {
+    int64_t v = ((int64_t)r.vgpr + 3) / 4 * 4 + r.agpr;
+    v = (v + 7) / 8 * 8;
+    int64_t waves = (threads + wave - 1) / wave;
+    return v * wave * waves;
+}
+
+Family matmul_family(int family, int dtype) {
+    Family f;
+    Syms m = add_machine(f);
+    if (family == PK_FAMILY_VALU) {
+        if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("VALU family: f32 and i32 only");
+        const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
+                  s = add_sym(f, "s", SYM_PROGRAM);
+        const int rho_t = add_sym(f, "rho_tiled", SYM_TABLE), rho_t1 = add_sym(f, "rho_tiled_s1", SYM_TABLE),
+                  rho_d = add_sym(f, "rho_direct", SYM_TABLE), rho_d1 = add_sym(f, "rho_direct_s1", SYM_TABLE);
+        const int64_t es = 4;  // element bytes (float32 and int32)
+        f.point_syms = {bx, by, s};
+        for (int x : kValuB)
+            for (int y : kValuB)
+                for (int z : kValuS) f.points.push_back({x, y, z});
+        // LDS bytes: A tile by x (bk + 1) and B tile bk x (bx * s), bk = by
+        const Poly lds_full = P(es) * (S(by) * (S(by) + P(1)) + S(by) * S(bx) * S(s));
+        const Poly lds_g1 = P(es) * (S(by) * (S(by) + P(1)) + S(by) * S(bx));
+        CounterDef rz{"r_Z", false, m.Z, nullptr};
+        rz.value = [=](uint32_t ap) {
+            if (ap & PK_VALU_NOLDS) return P(0);
+            if (ap & PK_VALU_GRAN) return lds_g1;
+            return lds_full;
+        };
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) {
+            const bool g = ap & PK_VALU_GRAN, d = ap & PK_VALU_NOLDS;
+            return S(d ? (g ? rho_d1 : rho_d) : (g ? rho_t1 : rho_t));
+        };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return S(bx) * S(by); };
+        f.counters = {rz, rv, rt};
+        f.strategies = {StrategyDef{"gran", false, 0b011u}, StrategyDef{"nolds", false, 0b011u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            int variant = 0;
+            if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
+            if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
+            return table_regs(PK_FAMILY_VALU, variant, dtype, pt, 64);
+        };
+        return f;
+    }
+    if (family == PK_FAMILY_MFMA) {
+        if (dtype != PK_F32 && dtype != PK_BF16) throw std::runtime_error("MFMA family: f32 and bf16 only");
+        const int bm = add_sym(f, "bm", SYM_PROGRAM), bn = add_sym(f, "bn", SYM_PROGRAM),
+                  bk = add_sym(f, "bk", SYM_PROGRAM), wm = add_sym(f, "wm", SYM_PROGRAM),
+                  wn = add_sym(f, "wn", SYM_PROGRAM);
+        const int rho2 = add_sym(f, "rho_two_stage", SYM_TABLE), rho1 = add_sym(f, "rho_one_stage", SYM_TABLE);
+        f.point_syms = {bm, bn, bk, wm, wn};
+        if (dtype == PK_F32)
+            for (const auto &p : kMfmaF32) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
+        else
+            for (const auto &p : kMfmaBf16) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
+        // one stage: f32  4 * (bm * (bk + 4) + bk * (bn + 4))
+        //            bf16 2 * (bm + bn) * (bk + 8)   (B stored transposed)
+        Poly stage = dtype == PK_F32 ? P(4) * (S(bm) * (S(bk) + P(4)) + S(bk) * (S(bn) + P(4)))
+                                     : P(2) * (S(bm) + S(bn)) * (S(bk) + P(8));
+        CounterDef rz{"r_Z", false, m.Z, nullptr};
+        rz.value = [=](uint32_t ap) { return (ap & PK_MFMA_SINGLE) ? stage : P(2) * stage; };
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) { return S((ap & PK_MFMA_SINGLE) ? rho1 : rho2); };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return P(64) * S(wm) * S(wn); };
+        f.counters = {rz, rv, rt};
+        f.strategies = {StrategyDef{"single", false, 0b011u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            return table_regs(PK_FAMILY_MFMA, sym == rho1 ? PK_MFMA_SINGLE : 0, dtype, pt, 64);
+        };
+        return f;
+    }
+    throw std::runtime_error("unknown family");
+}
+
+bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
+    if (family == PK_FAMILY_VALU) {
+        if (p.bk != 0 && p.bk != p.by) return false;  // the paper's K tile: bk = by
+        *pt = {p.bx, p.by, p.s};
+        return true;
+    }
+    if (family == PK_FAMILY_MFMA) {
+        *pt = {p.bm, p.bn, p.bk, p.wm, p.wn};
+        return true;
+    }
+    return false;
+}
+
+void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
+    p->family = family;
+    p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
+    if (family == PK_FAMILY_VALU) {
+        p->bx = (int32_t)pt[0];
+        p->by = (int32_t)pt[1];
+        p->s = (int32_t)pt[2];
+        p->bk = (int32_t)pt[1];
+    } else {
+        p->bm = (int32_t)pt[0];
+        p->bn = (int32_t)pt[1];
+        p->bk = (int32_t)pt[2];
+        p->wm = (int32_t)pt[3];
+        p->wn = (int32_t)pt[4];
+    }
+}
+
+std::vector<int64_t> machine_values(const Family &fam, const pk_machine &m) {
+    std::vector<int64_t> v(fam.sym_names.size(), 0);
+    v[fam.sym("Z")] = m.lds_block;
+    v[fam.sym("V")] = m.regs_block;
+    v[fam.sym("T")] = m.max_threads_block;
+    return v;
+}
+
+bool variant_fits(const Family &fam, uint32_t variant, const std::vector<int64_t> &pt,
+                  const std::vector<int64_t> &machine_vals) {
+    System sys;
+    for (const auto &c : fam.counters) {
+        if (c.performance) continue;
+        sys.push_back(Constraint{c.value(variant), Poly::symbol(c.limit), false});
+    }
+    return system_holds(fam, sys, pt, machine_vals);
+}
+
+const KernelEntry *find_instance(int family, int variant, int dtype, const std::vector<int64_t> &pt) {
+    // the program of a variant: VALU granularity reduction runs the s = 1
+    // instance; no-LDS runs the direct kernel; MFMA single runs one stage
+    int kind = 0;
+    std::vector<int64_t> q = pt;
+    if (family == PK_FAMILY_VALU) {
+        if (variant & PK_VALU_GRAN) q[2] = 1;
+        kind = variant & PK_VALU_NOLDS;
+    } else {
+        kind = variant & PK_MFMA_SINGLE;
+    }
+    for (const auto &e : registry()) {
+        if (e.family != family || e.dtype != dtype || e.variant != kind) continue;
+        if (family == PK_FAMILY_VALU) {
+            if (e.bx == q[0] && e.by == q[1] && e.s == q[2]) return &e;
+        } else {
+            if (e.bm == q[0] && e.bn == q[1] && e.bk == q[2] && e.wm == q[3] && e.wn == q[4]) return &e;
+        }
+    }
+    return nullptr;
+}
+
+}  // namespace pk

@@ -1,0 +1,34 @@
+// Argument block and registry record shared by the kernels and the host
+// library.  Plain data only.
+#pragma once
+
+#include <stdint.h>
+
+namespace pkk {
+
+// Arguments of every matmul kernel: C (MxN) = [C +] A (MxK) * B (KxN),
+// row-major with leading dimensions.  Pointers are device addresses.
+struct MmArgs {
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t accumulate;
+};
+
+// One compiled kernel instance, as listed by the generated registry.
+struct KernelEntry {
+    const char *name;
+    const void *fn;     // host stub of the __global__ function
+    int family;
+    int variant;        // strategy bits applied to the family's fragment
+    int dtype;          // pk_dtype
+    int bx, by, s, bk;  // VALU parameters (0 when unused)
+    int bm, bn, wm, wn; // MFMA parameters (0 when unused)
+    int threads;        // workgroup size
+    int lds_bytes;      // LDS the kernel allocates
+    int tile_m, tile_n; // output tile of one workgroup
+};
+
+}  // namespace pkk

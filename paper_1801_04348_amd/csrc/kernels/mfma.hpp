@@ -1,0 +1,371 @@
+// Matrix-core (MFMA) kernels of the matrix product for gfx950.
+//
+// Same contract as the VALU family (C = [C +] A B, row-major, any M, N, K),
+// used where the product is a dense contraction in float32 or bfloat16:
+//   float32:  v_mfma_f32_32x32x2_f32   (A 32x2, B 2x32, C 32x32 per wavefront)
+//   bfloat16: v_mfma_f32_32x32x16_bf16 (A 32x16, B 16x32, float32 accumulate)
+//
+// Decomposition: a workgroup of WM x WN wavefronts owns a BM x BN output tile;
+// each wavefront owns (BM/WM) x (BN/WN), i.e. TM x TN blocks of 32x32
+// accumulators (16 per lane each).  K advances in steps of BK through LDS:
+//   float32:  As[BM][BK+4]   (k contiguous),   Bs[BK][BN+4]   (n contiguous)
+//   bfloat16: As[BM][BK+8]   (k contiguous),   Bt[BN][BK+8]   (B transposed,
+//             k contiguous, so each lane reads its 8 k values with one 16-byte
+//             LDS load)
+// STAGES = 2 double-buffers the tiles (one barrier per K step: the next tile is
+// fetched from global memory into registers while the current one is
+// consumed); STAGES = 1 keeps one buffer and two barriers per step, as in the
+// paper's kernel.  LDS bytes = STAGES * (A tile + B tile).
+//
+// The order in which k enters each 32x32 block's sum is permuted: lanes 0-31
+// consume k in the first half of the LDS tile and lanes 32-63 the second half,
+// so a lane's operands are contiguous in LDS.  The set of products summed is
+// unchanged.
+//
+// Global loads are 16 bytes wide, so the leading dimensions must keep rows
+// 16-byte aligned (lda, ldb multiples of 4 floats / 8 bfloat16 and 16-byte
+// aligned bases); the host checks this.  Tiles crossing the matrix edge use
+// guarded element loads with zero fill and guarded stores.
+//
+// Workgroup -> tile map: workgroups are dispatched round-robin over the 8 XCDs
+// (each with its own L2); blocks b and b+8 land on the same XCD, so the map
+// first gives each XCD a contiguous range of tile indices and then walks that
+// range in groups of GROUP_M tile rows, which keeps the A and B panels an XCD
+// reads within its L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kargs.hpp"
+
+namespace pkk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int XCDS = 8;
+constexpr int GROUP_M = 8;
+
+// tile (tm, tn) of linear workgroup b among tiles_m x tiles_n
+__device__ __forceinline__ void tile_of(int64_t b, int tiles_m, int tiles_n, int *tm, int *tn) {
+    const int64_t T = (int64_t)tiles_m * tiles_n;
+    const int64_t q = T / XCDS;
+    int64_t pid = b;
+    if (b < q * XCDS) pid = (b % XCDS) * q + b / XCDS;
+    const int64_t width = (int64_t)GROUP_M * tiles_n;
+    const int64_t group = pid / width;
+    const int first_m = (int)(group * GROUP_M);
+    const int gm = min(tiles_m - first_m, GROUP_M);
+    const int64_t in = pid % width;
+    *tm = first_m + (int)(in % gm);
+    *tn = (int)(in / gm);
+}
+
+// ------------------------------------------------------------------ float32
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void mfma_f32(const MmArgs &a) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 32, TN = WTN / 32;
+    constexpr int PA = 4, PB = 4;
+    constexpr int LDA_S = BK + PA, LDB_S = BN + PB;
+    constexpr int A4 = BM * BK / 4 / NT;  // float4 loads per work-item per A tile
+    constexpr int B4 = BK * BN / 4 / NT;
+    static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
+    static_assert(A4 >= 1 && B4 >= 1 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tile loads");
+    static_assert(BK % 8 == 0, "BK");
+
+    __shared__ __attribute__((aligned(16))) float As[STAGES][BM * LDA_S];
+    __shared__ __attribute__((aligned(16))) float Bs[STAGES][BK * LDB_S];
+
+    const float *__restrict__ A = static_cast<const float *>(a.A);
+    const float *__restrict__ B = static_cast<const float *>(a.B);
+    float *__restrict__ C = static_cast<float *>(a.C);
+    const int M = a.M, N = a.N, K = a.K;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int r = lane & 31, h = lane >> 5;
+
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+    const int row0 = tm * BM, col0 = tn * BN;
+    const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+    f32x4 ra[A4], rb[B4];
+    auto gload = [&](int k0) {
+        const bool kfull = (k0 + BK <= K);
+#pragma unroll
+        for (int u = 0; u < A4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+            const int gr = row0 + rr, gc = k0 + c4;
+            if (kfull && (interior || gr < M)) {
+                ra[u] = *reinterpret_cast<const f32x4 *>(A + (int64_t)gr * a.lda + gc);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+            const int gr = k0 + rr, gc = col0 + c4;
+            if (gr < K && (interior || gc + 4 <= N)) {
+                rb[u] = *reinterpret_cast<const f32x4 *>(B + (int64_t)gr * a.ldb + gc);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    rb[u][e] = (gr < K && gc + e < N) ? B[(int64_t)gr * a.ldb + gc + e] : 0.0f;
+            }
+        }
+    };
+    auto sstore = [&](int st) {
+#pragma unroll
+        for (int u = 0; u < A4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+            *reinterpret_cast<f32x4 *>(&As[st][rr * LDA_S + c4]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < B4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+            *reinterpret_cast<f32x4 *>(&Bs[st][rr * LDB_S + c4]) = rb[u];
+        }
+    };
+    auto compute = [&](int st) {
+        const float *as = &As[st][(wm * WTM + r) * LDA_S + h * (BK / 2)];
+        const float *bs = &Bs[st][(h * (BK / 2)) * LDB_S + wn * WTN + r];
+#pragma unroll
+        for (int kc = 0; kc < BK / 2; kc += 4) {
+            f32x4 af[TM];
+            float bf[TN][4];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const f32x4 *>(as + i * 32 * LDA_S + kc);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bf[j][q] = bs[(kc + q) * LDB_S + j * 32];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][q], bf[j][q], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    const int KT = (K + BK - 1) / BK;
+    if (STAGES == 2) {
+        if (KT > 0) {
+            gload(0);
+            sstore(0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            compute(cur);
+            if (kt + 1 < KT) sstore(cur ^ 1);
+            __syncthreads();
+        }
+    } else {
+        for (int kt = 0; kt < KT; ++kt) {
+            gload(kt * BK);
+            __syncthreads();
+            sstore(0);
+            __syncthreads();
+            compute(0);
+        }
+    }
+
+    // epilogue: value v of block (i, j) is row 8*(v/4) + 4*h + v%4, column r
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int gc = col0 + wn * WTN + j * 32 + r;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
+                if (interior || (gr < M && gc < N)) {
+                    float *p = C + (int64_t)gr * a.ldc + gc;
+                    *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
+                }
+            }
+        }
+}
+
+// ------------------------------------------------------------------ bfloat16
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN;
+    constexpr int TM = WTM / 32, TN = WTN / 32;
+    constexpr int P = 8;
+    constexpr int LD_S = BK + P;                 // row stride (elements) of As and Bt
+    constexpr int A8 = BM * BK / 8 / NT;         // 16-byte loads per work-item per A tile
+    constexpr int B8 = (BK / 8) * (BN / 2) / NT; // (8 k rows x 2 columns) blocks per work-item
+    static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
+    static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && ((BK / 8) * (BN / 2)) % NT == 0, "tile loads");
+    static_assert(BK % 32 == 0, "BK");
+
+    __shared__ __attribute__((aligned(16))) unsigned short As[STAGES][BM * LD_S];
+    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES][BN * LD_S];
+
+    const unsigned short *__restrict__ A = static_cast<const unsigned short *>(a.A);
+    const unsigned short *__restrict__ B = static_cast<const unsigned short *>(a.B);
+    float *__restrict__ C = static_cast<float *>(a.C);
+    const int M = a.M, N = a.N, K = a.K;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int r = lane & 31, h = lane >> 5;
+
+    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int tm, tn;
+    tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+    const int row0 = tm * BM, col0 = tn * BN;
+    const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+    u16x8 ra[A8];
+    unsigned int rb[B8][8];  // 8 k rows of a column pair (n, n+1)
+    auto gload = [&](int k0) {
+        const bool kfull = (k0 + BK <= K);
+#pragma unroll
+        for (int u = 0; u < A8; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+            const int gr = row0 + rr, gc = k0 + c8;
+            if (kfull && (interior || gr < M)) {
+                ra[u] = *reinterpret_cast<const u16x8 *>(A + (int64_t)gr * a.lda + gc);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : (unsigned short)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int f = tid + u * NT;
+            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;  // column pair, first k row
+            const int gc = col0 + cp;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int gr = k0 + kr + e;
+                if (gr < K && (interior || gc + 2 <= N)) {
+                    rb[u][e] = *reinterpret_cast<const unsigned int *>(B + (int64_t)gr * a.ldb + gc);
+                } else {
+                    unsigned int lo = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : 0u;
+                    unsigned int hi = (gr < K && gc + 1 < N) ? B[(int64_t)gr * a.ldb + gc + 1] : 0u;
+                    rb[u][e] = lo | (hi << 16);
+                }
+            }
+        }
+    };
+    auto sstore = [&](int st) {
+#pragma unroll
+        for (int u = 0; u < A8; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+            *reinterpret_cast<u16x8 *>(&As[st][rr * LD_S + c8]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int f = tid + u * NT;
+            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
+            u32x4 lo, hi;  // column cp and cp + 1, 8 k values each
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned int w0 = rb[u][2 * e], w1 = rb[u][2 * e + 1];
+                lo[e] = (w0 & 0xffffu) | (w1 << 16);
+                hi[e] = (w0 >> 16) | (w1 & 0xffff0000u);
+            }
+            *reinterpret_cast<u32x4 *>(&Bt[st][cp * LD_S + kr]) = lo;
+            *reinterpret_cast<u32x4 *>(&Bt[st][(cp + 1) * LD_S + kr]) = hi;
+        }
+    };
+    auto compute = [&](int st) {
+        const unsigned short *as = &As[st][(wm * WTM + r) * LD_S + h * (BK / 2)];
+        const unsigned short *bs = &Bt[st][(wn * WTN + r) * LD_S + h * (BK / 2)];
+#pragma unroll
+        for (int kc = 0; kc < BK / 2; kc += 8) {
+            bf16x8 af[TM], bf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(as + i * 32 * LD_S + kc);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bf[j] = *reinterpret_cast<const bf16x8 *>(bs + j * 32 * LD_S + kc);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    const int KT = (K + BK - 1) / BK;
+    if (STAGES == 2) {
+        if (KT > 0) {
+            gload(0);
+            sstore(0);
+        }
+        __syncthreads();
+        for (int kt = 0; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            compute(cur);
+            if (kt + 1 < KT) sstore(cur ^ 1);
+            __syncthreads();
+        }
+    } else {
+        for (int kt = 0; kt < KT; ++kt) {
+            gload(kt * BK);
+            __syncthreads();
+            sstore(0);
+            __syncthreads();
+            compute(0);
+        }
+    }
+
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int gc = col0 + wn * WTN + j * 32 + r;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
+                if (interior || (gr < M && gc < N)) {
+                    float *p = C + (int64_t)gr * a.ldc + gc;
+                    *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
+                }
+            }
+        }
+}
+
+}  // namespace pkk

@@ -1,0 +1,155 @@
+// VALU kernels of the blocked matrix product (Section 2, Fig. 3 and Fig. 4),
+// written for gfx950.
+//
+// Work decomposition (Fig. 3): a workgroup of BX x BY work-items owns an
+// output tile of BY rows and BX*S columns.  Work-item (ty, tx) computes the S
+// outputs C[row0 + ty][col0 + tx + w*BX], w < S, so consecutive lanes write
+// consecutive columns (coalesced, as the paper notes for its a, b, c accesses).
+// Tiles are visited with a workgroup-stride loop over the linear tile index
+// (the paper strides its blocks by a fixed 256; here the stride is the grid).
+//
+// valu_tiled (no strategy applied; or at S = 1 after granularity reduction):
+//   per K step of BK, the workgroup stages the A tile (BY x BK) and the B tile
+//   (BK x BX*S) in LDS with cooperative, coalesced loads (zero fill outside
+//   the matrices), synchronises, accumulates from LDS, synchronises again --
+//   the two barriers per K tile of Fig. 4.  The A tile rows are padded by one
+//   element so the BY rows a wavefront reads at the same k fall in different
+//   banks.  LDS bytes: esize * (BY * (BK + 1) + BK * BX * S).
+// valu_direct (decision (4b), no LDS): every work-item reads its A row and B
+//   columns from global memory (the A element is common to the lanes of a
+//   row, the B elements are contiguous across lanes).
+//
+// Arithmetic: float32 accumulates with fused multiply-add in k order starting
+// from C (accumulate) or 0; int32 accumulates in uint32, i.e. modulo 2^32.
+// Any M, N, K >= 0 is handled: loads are guarded and stores are guarded.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kargs.hpp"
+
+namespace pkk {
+
+template <typename T> struct Acc;
+template <> struct Acc<float> {
+    using type = float;
+    static __device__ __forceinline__ float from(float x) { return x; }
+    static __device__ __forceinline__ float to(float x) { return x; }
+    static __device__ __forceinline__ float mad(float acc, float a, float b) { return __builtin_fmaf(a, b, acc); }
+};
+template <> struct Acc<int32_t> {
+    using type = uint32_t;
+    static __device__ __forceinline__ uint32_t from(int32_t x) { return (uint32_t)x; }
+    static __device__ __forceinline__ int32_t to(uint32_t x) { return (int32_t)x; }
+    static __device__ __forceinline__ uint32_t mad(uint32_t acc, uint32_t a, uint32_t b) { return acc + a * b; }
+};
+
+template <typename T, int BX, int BY, int S, int BK>
+__device__ __forceinline__ void valu_tiled(const MmArgs &a) {
+    using U = typename Acc<T>::type;
+    constexpr int NT = BX * BY;
+    constexpr int TM = BY;
+    constexpr int TN = BX * S;
+    __shared__ T As[TM][BK + 1];
+    __shared__ T Bs[BK][TN];
+
+    const T *__restrict__ A = static_cast<const T *>(a.A);
+    const T *__restrict__ B = static_cast<const T *>(a.B);
+    T *__restrict__ C = static_cast<T *>(a.C);
+    const int M = a.M, N = a.N, K = a.K;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int tiles_n = (N + TN - 1) / TN;
+    const int64_t tiles = (int64_t)((M + TM - 1) / TM) * tiles_n;
+
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int row0 = (int)(t / tiles_n) * TM;
+        const int col0 = (int)(t % tiles_n) * TN;
+        const int row = row0 + ty;
+        U acc[S];
+#pragma unroll
+        for (int w = 0; w < S; ++w) {
+            const int col = col0 + tx + w * BX;
+            acc[w] = (a.accumulate && row < M && col < N) ? Acc<T>::from(C[(int64_t)row * a.ldc + col]) : U(0);
+        }
+        for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+            for (int u = 0; u < (TM * BK + NT - 1) / NT; ++u) {
+                const int e = tid + u * NT;
+                if ((TM * BK) % NT == 0 || e < TM * BK) {
+                    const int r = e / BK, c = e % BK;
+                    const int gr = row0 + r, gc = k0 + c;
+                    As[r][c] = (gr < M && gc < K) ? A[(int64_t)gr * a.lda + gc] : T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < (BK * TN + NT - 1) / NT; ++u) {
+                const int e = tid + u * NT;
+                if ((BK * TN) % NT == 0 || e < BK * TN) {
+                    const int r = e / TN, c = e % TN;
+                    const int gr = k0 + r, gc = col0 + c;
+                    Bs[r][c] = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : T(0);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk) {
+                const U av = (U)As[ty][kk];
+#pragma unroll
+                for (int w = 0; w < S; ++w) acc[w] = Acc<T>::mad(acc[w], av, (U)Bs[kk][tx + w * BX]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int w = 0; w < S; ++w) {
+            const int col = col0 + tx + w * BX;
+            if (row < M && col < N) C[(int64_t)row * a.ldc + col] = Acc<T>::to(acc[w]);
+        }
+    }
+}
+
+template <typename T, int BX, int BY, int S>
+__device__ __forceinline__ void valu_direct(const MmArgs &a) {
+    using U = typename Acc<T>::type;
+    constexpr int TM = BY;
+    constexpr int TN = BX * S;
+    const T *__restrict__ A = static_cast<const T *>(a.A);
+    const T *__restrict__ B = static_cast<const T *>(a.B);
+    T *__restrict__ C = static_cast<T *>(a.C);
+    const int M = a.M, N = a.N, K = a.K;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int tiles_n = (N + TN - 1) / TN;
+    const int64_t tiles = (int64_t)((M + TM - 1) / TM) * tiles_n;
+
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int row = (int)(t / tiles_n) * TM + ty;
+        const int col0 = (int)(t % tiles_n) * TN + tx;
+        if (row >= M) continue;
+        U acc[S];
+#pragma unroll
+        for (int w = 0; w < S; ++w) {
+            const int col = col0 + w * BX;
+            acc[w] = (a.accumulate && col < N) ? Acc<T>::from(C[(int64_t)row * a.ldc + col]) : U(0);
+        }
+        const T *arow = A + (int64_t)row * a.lda;
+        for (int k = 0; k < K; ++k) {
+            const U av = (U)arow[k];
+            const T *brow = B + (int64_t)k * a.ldb;
+#pragma unroll
+            for (int w = 0; w < S; ++w) {
+                const int col = col0 + w * BX;
+                const U bv = col < N ? (U)brow[col] : U(0);
+                acc[w] = Acc<T>::mad(acc[w], av, bv);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < S; ++w) {
+            const int col = col0 + w * BX;
+            if (col < N) C[(int64_t)row * a.ldc + col] = Acc<T>::to(acc[w]);
+        }
+    }
+}
+
+}  // namespace pkk

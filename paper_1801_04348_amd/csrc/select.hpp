@@ -1,0 +1,41 @@
+// Load-time selection of a leaf and its program parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pk_internal.hpp"
+
+namespace pk {
+
+// One feasible choice: a leaf of a family's table that holds at the bound
+// machine and at the program parameters of the point, with its instance.
+struct Candidate {
+    int family = 0;
+    int point = 0;   // index into the family's point list
+    int leaf = -1;
+    int variant = 0;
+    const KernelEntry *entry = nullptr;
+    double estimate = 0.0;  // analytic time estimate, seconds
+};
+
+// The feasible set F for (dtype, M, N, K).  When `A` is given, MFMA
+// candidates whose alignment conditions fail are left out.
+std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
+                                const void *A = nullptr, int64_t lda = 0, const void *B = nullptr,
+                                int64_t ldb = 0);
+
+// Analytic time of one launch (the CASE score).
+double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K);
+
+int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, int policy, bool cache,
+                  pk_params *out, const void *A = nullptr, int64_t lda = 0, const void *B = nullptr,
+                  int64_t ldb = 0);
+
+// helpers shared with capi.cpp
+int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);
+int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
+bool data_ok(int family, int dtype, const void *A, int64_t lda, const void *B, int64_t ldb);
+int launch(const pk_machine &m, const KernelEntry &e, const MmArgs &args, hipStream_t stream);
+void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out);
+
+}  // namespace pk

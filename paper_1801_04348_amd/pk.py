@@ -1,0 +1,239 @@
+"""ctypes binding of libpk.so: the same entry points as include/pk.h.
+
+Argument marshalling only -- every step of the path runs in the library and
+its HIP kernels.  Matrices may be passed as torch tensors (device memory);
+their data pointers, leading dimensions and the current HIP stream are
+forwarded.  Importing this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpk.so")
+
+PK_OK = 0
+PK_ERR_INVALID_ARG = -1
+PK_ERR_NO_FEASIBLE_BRANCH = -2
+PK_ERR_UNSUPPORTED_DTYPE = -3
+PK_ERR_NOT_INSTANTIATED = -4
+PK_ERR_HIP = -5
+PK_ERR_COST_MODEL = -6
+PK_ERR_BUFFER_TOO_SMALL = -7
+PK_ERR_PARSE = -8
+
+PK_F32, PK_I32, PK_BF16 = 0, 1, 2
+PK_FAMILY_VALU, PK_FAMILY_MFMA = 0, 1
+PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
+PK_MFMA_SINGLE = 1
+PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
+
+DTYPES = {"f32": PK_F32, "i32": PK_I32, "bf16": PK_BF16}
+
+
+class PkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("pk error %d: %s" % (code, msg))
+        self.code = code
+
+
+class pk_machine(ctypes.Structure):
+    _fields_ = [("wave", ctypes.c_int32), ("lds_block", ctypes.c_int64), ("lds_cu", ctypes.c_int64),
+                ("regs_block", ctypes.c_int64), ("regs_cu", ctypes.c_int64),
+                ("max_threads_block", ctypes.c_int32), ("max_threads_cu", ctypes.c_int32),
+                ("max_blocks_cu", ctypes.c_int32), ("cu_count", ctypes.c_int32),
+                ("clock_khz", ctypes.c_int32), ("arch", ctypes.c_char * 64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["arch"] = self.arch.decode()
+        return d
+
+
+class pk_params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("family", "leaf", "variant", "bx", "by", "s", "bk", "bm", "bn", "wm", "wn")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    def __repr__(self):
+        return "pk_params(%s)" % ", ".join("%s=%d" % kv for kv in self.as_dict().items())
+
+
+def params(family=PK_FAMILY_VALU, leaf=-1, variant=-1, bx=0, by=0, s=0, bk=0, bm=0, bn=0, wm=0, wn=0):
+    return pk_params(family, leaf, variant, bx, by, s, bk, bm, bn, wm, wn)
+
+
+def machine(**kw) -> pk_machine:
+    m = pk_machine()
+    for k, v in kw.items():
+        if k == "arch":
+            m.arch = v.encode() if isinstance(v, str) else v
+        else:
+            setattr(m, k, v)
+    return m
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpk.so is not built; run __graft_entry__.build() (or python -m "
+                               "paper_1801_04348_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+        L.pk_last_error.restype = ctypes.c_char_p
+        L.pk_version.restype = ctypes.c_char_p
+        L.pk_instance_count.restype = i32
+        L.pk_instance_name.restype = ctypes.c_char_p
+        L.pk_instance_name.argtypes = [i32]
+        L.pk_machine_query.argtypes = [i32, ctypes.POINTER(pk_machine)]
+        L.pk_co_solve.argtypes = [ctypes.c_char_p, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+        L.pk_case_table_build.argtypes = [i32, ctypes.POINTER(pk_machine), ctypes.POINTER(vp)]
+        L.pk_case_table_free.argtypes = [vp]
+        L.pk_case_table_free.restype = None
+        L.pk_case_table_describe.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+        L.pk_case_table_lookup.argtypes = [vp, i32, ctypes.POINTER(pk_params), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32)]
+        L.pk_select.argtypes = [vp, i32, i64, i64, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_matmul.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, vp, i64, i64, i64, i64,
+                                i32, vp]
+        L.pk_launch_shape.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64,
+                                      ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
+        for name in ("pk_machine_query", "pk_co_solve", "pk_case_table_build", "pk_case_table_describe",
+                     "pk_case_table_lookup", "pk_select", "pk_matmul", "pk_launch_shape"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PK_OK:
+        raise PkError(rc, lib().pk_last_error().decode(errors="replace"))
+    return rc
+
+
+def last_error() -> str:
+    return lib().pk_last_error().decode(errors="replace")
+
+
+def pk_version() -> str:
+    return lib().pk_version().decode()
+
+
+def pk_instance_names():
+    L = lib()
+    return [L.pk_instance_name(i).decode() for i in range(L.pk_instance_count())]
+
+
+def pk_machine_query(device: int = 0) -> pk_machine:
+    m = pk_machine()
+    _check(lib().pk_machine_query(device, ctypes.byref(m)))
+    return m
+
+
+def _text_call(fn, *args):
+    need = ctypes.c_size_t(0)
+    rc = fn(*args, None, 0, ctypes.byref(need))
+    if rc not in (PK_OK, PK_ERR_BUFFER_TOO_SMALL):
+        _check(rc)
+    buf = ctypes.create_string_buffer(need.value)
+    _check(fn(*args, buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def pk_co_solve(spec: str) -> dict:
+    """Algorithms 1 and 2 on a family given in the library's text format."""
+    return json.loads(_text_call(lib().pk_co_solve, spec.encode()))
+
+
+class Table:
+    """Owner of a pk_table handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.pk_case_table_free(h)
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def pk_case_table_build(device: int = 0, override: pk_machine | None = None) -> Table:
+    h = ctypes.c_void_p()
+    _check(lib().pk_case_table_build(device, ctypes.byref(override) if override is not None else None,
+                                     ctypes.byref(h)))
+    return Table(h)
+
+
+def pk_case_table_describe(tbl: Table) -> dict:
+    return json.loads(_text_call(lib().pk_case_table_describe, tbl.handle))
+
+
+def pk_case_table_lookup(tbl: Table, dtype, p: pk_params):
+    """(leaf, variant) at program parameters p, or raises PkError."""
+    leaf, var = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    _check(lib().pk_case_table_lookup(tbl.handle, _dt(dtype), ctypes.byref(p), ctypes.byref(leaf),
+                                      ctypes.byref(var)))
+    return leaf.value, var.value
+
+
+def _dt(dtype) -> int:
+    return DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+
+
+def pk_select(tbl: Table, dtype, M: int, N: int, K: int, policy: int = PK_POLICY_CASE,
+              allow_fallback: bool = False) -> pk_params:
+    out = pk_params()
+    rc = lib().pk_select(tbl.handle, _dt(dtype), M, N, K, policy, ctypes.byref(out))
+    if rc == PK_ERR_COST_MODEL and allow_fallback:
+        return out
+    _check(rc)
+    return out
+
+
+def pk_launch_shape(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):
+    g, b, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().pk_launch_shape(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, ctypes.byref(g),
+                                 ctypes.byref(b), ctypes.byref(l)))
+    return g.value, b.value, l.value
+
+
+def _ptr_ld(t):
+    """Device pointer and leading dimension of a row-major 2-D tensor."""
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D with unit column stride")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=None):
+    """C = [C +] A @ B on the device.  A: (M, K), B: (K, N), C: (M, N) torch
+    tensors; for bf16, A and B hold bfloat16 (or int16 bit patterns) and C is
+    float32.  p: a pk_params, or None for the CASE choice."""
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise ValueError("shape mismatch: A %s, B %s, C %s" % (tuple(A.shape), tuple(B.shape), tuple(C.shape)))
+    a, lda = _ptr_ld(A)
+    b, ldb = _ptr_ld(B)
+    c, ldc = _ptr_ld(C)
+    _check(lib().pk_matmul(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype),
+                           a, max(lda, K), b, max(ldb, N), c, max(ldc, N), M, N, K,
+                           1 if accumulate else 0, _stream(stream)))

@@ -1,0 +1,250 @@
+"""Host-side tests of libpk.so (no GPU): exported symbols, the symbolic
+engine against the oracle and the paper's printed systems, and the bound
+matmul case tables against the oracle's brute-force enumerator."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle.comprehensive as co
+import oracle.enumerate as en
+from paper_1801_04348_amd import pk
+from tests import machines
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "pk.h")) as f:
+        text = f.read()
+    decls = set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_]+\s*\*?\s*(pk_[a-z_]+)\s*\(", text, re.M))
+    assert {"pk_case_table_build", "pk_select", "pk_matmul", "pk_co_solve"} <= decls
+    L = pk.lib()
+    for name in sorted(decls):
+        assert hasattr(L, name), name
+
+
+def _spec_text(spec):
+    """The golden JSON family in the library's text format."""
+    sy = spec["symbols"]
+    lines = ["machine " + " ".join(sy["machine"]), "program " + " ".join(sy["program"])]
+    if sy.get("data"):
+        lines.append("data " + " ".join(sy["data"]))
+    for s, d in spec["domains"].items():
+        if isinstance(d, dict):
+            lines.append("domain %s %d %d" % (s, d["lo"], d["hi"]))
+        else:
+            lines.append("points %s %s" % (s, " ".join(map(str, d))))
+    for c in spec["counters"]:
+        lines.append("counter %s %s %s" % (c["name"], c["kind"], c["limit"]))
+    for c in spec["counters"]:
+        for v in c["values"]:
+            lines.append("value %s %s : %s" % (c["name"], " ".join(v["when"]), v["value"]))
+    for o in spec["strategies"]:
+        lines.append("strategy %s %s %s" % (o["name"], "ir" if o["ir"] else "src", " ".join(o["sigma"])))
+    if "perf_one" in spec:
+        lines.append("perf_one %d" % spec["perf_one"])
+    return "\n".join(lines) + "\n"
+
+
+def _poly(js):
+    return co.Poly({tuple(sorted((s, e) for s, e in mono)): c for c, mono in js})
+
+
+def _lib_leaves(res):
+    out = []
+    for l in res["leaves"]:
+        C = [co.Constraint(_poly(c["lhs"]), _poly(c["rhs"]), c["strict"]) for c in l["system"]]
+        out.append((tuple(l["applied"]), tuple(l["lambda"]), C))
+    return out
+
+
+def _same_leaves(lib_leaves, oracle_leaves):
+    assert len(lib_leaves) == len(oracle_leaves)
+    for (a1, l1, C1), (a2, l2, C2) in zip(lib_leaves, oracle_leaves):
+        # compare G_C (source strategies in order) and lambda separately
+        assert tuple(a for a in a1 if a not in l1) == tuple(a for a in a2 if a not in l2)
+        assert tuple(l1) == tuple(l2)
+        assert [c.normal() for c in C1] == [c.normal() for c in C2]
+
+
+@pytest.mark.parametrize("name", ["fig2_matrix_add", "fig6_jacobi", "fig7_transpose"])
+def test_engine_matches_oracle_on_printed_examples(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        spec = json.load(f)
+    fam = co.family_from_spec(spec)
+    res = pk.pk_co_solve(_spec_text(spec))
+    lib_leaves = _lib_leaves(res)
+    _same_leaves(lib_leaves, co.solve(fam))
+    assert res["height"] == co.tree_height(fam)
+    # and directly against the printed systems
+    for exp in spec["expected"]:
+        want = co.parse_system(exp["system"])
+        same = [l for l in lib_leaves if tuple(a for a in l[0] if a not in l[1]) == tuple(exp["variant"])]
+        if exp["match"] == "exact":
+            assert any(co.equivalent(l[2], want, fam) for l in same), exp
+        else:
+            assert any(co.implies(want, l[2], fam) for l in same), exp
+
+
+def test_engine_performance_counter_branch():
+    spec = ("machine R P\nprogram b\ndomain R 0 11\ndomain P 0 100\npoints b 1 2\n"
+            "counter r resource R\ncounter p performance P\nvalue r : 4*b\nvalue p x : 100\nvalue p : 50\n"
+            "strategy x src p\nperf_one 100\n")
+    res = pk.pk_co_solve(spec)
+    assert len(res["leaves"]) == 1 and res["leaves"][0]["applied"] == []
+    texts = [c["text"] for c in res["leaves"][0]["system"]]
+    assert "50 <= P" in texts and "4*b <= R" in texts
+
+
+def test_engine_parse_errors():
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_co_solve("machine R\ncounter r resource Q\n")
+    assert e.value.code == pk.PK_ERR_PARSE
+
+
+@pytest.fixture(scope="module")
+def gfx_table():
+    return pk.pk_case_table_build(0, machines.gfx950())
+
+
+@pytest.fixture(scope="module")
+def gfx_desc(gfx_table):
+    return pk.pk_case_table_describe(gfx_table)
+
+
+def test_lds_counter_equals_compiled_lds(gfx_desc):
+    for e in gfx_desc["instances"]:
+        assert e["lds_bytes"] == e["lds_compiled"], e["name"]
+        if e["family"] == en.VALU:
+            assert e["lds_bytes"] == en.valu_lds(e["variant"], e["bx"], e["by"], e["s"])
+        else:
+            assert e["lds_bytes"] == en.mfma_lds(e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"])
+        assert e["scratch"] == 0, e["name"]   # no register spills in any instance
+
+
+def test_matmul_tables_match_oracle_algorithm(gfx_desc):
+    inst = en.InstanceData(gfx_desc["instances"])
+    for part in gfx_desc["parts"]:
+        fam = en.oracle_family(part["family"], part["dtype"], [tuple(p) for p in part["points"]], inst)
+        _same_leaves(_lib_leaves(part["solution"]), co.solve(fam))
+        # table symbols: the library's register figures equal the oracle's
+        for sym, vals in part["tables"].items():
+            got = fam.tables[sym]({s: np.array([p[k] for p in part["points"]])
+                                   for k, s in enumerate(fam.program)})
+            assert list(got) == vals, sym
+
+
+def _check_part(part, inst, m):
+    """Completeness, soundness and preference of one bound part."""
+    fam_id, dt = part["family"], part["dtype"]
+    leaves = part["solution"]["leaves"]
+    Z, V, T = m.lds_block, m.regs_block, m.max_threads_block
+    used = set()
+    for i, p in enumerate(part["points"]):
+        p = tuple(p)
+        some = [v for v in en.variants(fam_id) if en.fits(inst, fam_id, dt, v, p, Z, V, T)]
+        leaf = part["first_leaf"][i]
+        if some:
+            assert leaf >= 0, (fam_id, dt, p, some)                   # completeness
+        if leaf >= 0:
+            var = leaves[leaf]["variant"]
+            assert en.fits(inst, fam_id, dt, var, p, Z, V, T), (p, var)  # soundness
+            used.add(leaf)
+            if 0 in some:
+                assert var == 0, (p, var)                              # preference
+    return used
+
+
+def test_enumerator_over_machine_grid(gfx_desc):
+    inst = en.InstanceData(gfx_desc["instances"])
+    used = {}
+    for Z, V, T in en.machine_grid():
+        t = pk.pk_case_table_build(0, machines.grid_machine(Z, V, T))
+        d = pk.pk_case_table_describe(t)
+        for part in d["parts"]:
+            key = (part["family"], part["dtype"])
+            used.setdefault(key, set()).update(_check_part(part, inst, machines.grid_machine(Z, V, T)))
+    for part in gfx_desc["parts"]:
+        n = len(part["solution"]["leaves"])
+        key = (part["family"], part["dtype"])
+        # no dead leaves: every leaf is selected somewhere on the grid, except
+        # register-refusal leaves whose programs never use fewer registers
+        dead = [l for l in range(n) if l not in used[key]]
+        for l in dead:
+            leaf = part["solution"]["leaves"][l]
+            assert any("V <" in c["text"] for c in leaf["system"]), leaf
+
+
+@pytest.mark.parametrize("mk", [machines.gfx950, machines.mi300x_like, machines.fermi_like])
+def test_named_machines(mk, gfx_desc):
+    inst = en.InstanceData(gfx_desc["instances"])
+    m = mk()
+    d = pk.pk_case_table_describe(pk.pk_case_table_build(0, m))
+    for part in d["parts"]:
+        _check_part(part, inst, m)
+
+
+def test_optimality_definition_3_iv(gfx_desc):
+    # for each counter, some leaf at which no strategy of sigma(counter) is
+    # left unapplied (so none can lower it further)
+    sigma = {0: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
+             1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()}}
+    for part in gfx_desc["parts"]:
+        for counter, strategies in sigma[part["family"]].items():
+            assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
+
+
+def test_height_bound(gfx_desc):
+    for part in gfx_desc["parts"]:
+        s, t, w = len(part["counters"]), 0, len(part["strategies"])
+        assert part["solution"]["height"] <= (s + t) + w * (s + 1)
+
+
+def test_mi300x_like_drops_to_single_stage():
+    # with 64 KiB of LDS the two-stage 256x256 float32 tile (137 KiB) is
+    # refused and the one-stage program (69 KiB) still does not fit: no leaf;
+    # 128x128 two-stage (69 KiB) is refused, one-stage (34.5 KiB) fits
+    t = pk.pk_case_table_build(0, machines.mi300x_like())
+    big = pk.params(family=pk.PK_FAMILY_MFMA, bm=256, bn=256, bk=32, wm=4, wn=4)
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_case_table_lookup(t, "f32", big)
+    assert e.value.code == pk.PK_ERR_NO_FEASIBLE_BRANCH
+    mid = pk.params(family=pk.PK_FAMILY_MFMA, bm=128, bn=128, bk=32, wm=2, wn=2)
+    leaf, var = pk.pk_case_table_lookup(t, "f32", mid)
+    assert var == pk.PK_MFMA_SINGLE
+    g = pk.pk_case_table_build(0, machines.gfx950())
+    assert pk.pk_case_table_lookup(g, "f32", big)[1] == 0
+
+
+def test_select_returns_feasible_choice(gfx_table):
+    for dt in ("f32", "i32", "bf16"):
+        for shp in [(1, 1, 1), (256, 256, 256), (1000, 3000, 512), (8192, 8192, 8192)]:
+            p = pk.pk_select(gfx_table, dt, *shp)
+            leaf, var = pk.pk_case_table_lookup(gfx_table, dt, p)
+            assert leaf == p.leaf and var == p.variant
+
+
+def test_select_no_feasible_branch():
+    t = pk.pk_case_table_build(0, machines.variant(max_threads_block=8))
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_select(t, "i32", 64, 64, 64)
+    assert e.value.code == pk.PK_ERR_NO_FEASIBLE_BRANCH
+
+
+def test_matmul_argument_errors_without_gpu(gfx_table):
+    L = pk.lib()
+    rc = L.pk_matmul(gfx_table.handle, None, 0, None, 4, None, 4, None, 4, -1, 4, 4, 0, None)
+    assert rc == pk.PK_ERR_INVALID_ARG
+    rc = L.pk_matmul(gfx_table.handle, None, 0, 8, 2, 8, 4, 8, 4, 4, 4, 4, 0, None)  # lda < K
+    assert rc == pk.PK_ERR_INVALID_ARG
+    rc = L.pk_matmul(gfx_table.handle, None, 0, None, 4, None, 4, None, 4, 0, 4, 4, 0, None)  # M == 0
+    assert rc == pk.PK_OK
+    rc = L.pk_matmul(None, None, 0, None, 4, None, 4, None, 4, 4, 4, 4, 0, None)
+    assert rc == pk.PK_ERR_INVALID_ARG
+    bad = pk.params(family=pk.PK_FAMILY_MFMA, bm=64, bn=64, bk=32, wm=2, wn=2)
+    rc = L.pk_matmul(gfx_table.handle, bad, pk.PK_I32, 16, 4, 16, 4, 16, 4, 4, 4, 4, 0, None)
+    assert rc == pk.PK_ERR_UNSUPPORTED_DTYPE
