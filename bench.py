@@ -1,0 +1,230 @@
+"""Benchmark: float32 matmul throughput of the case-table pick over the
+216-shape sweep M, N, K in {512, 1000, 2048, 3000, 4096, 8192}, against the
+exhaustively-best branch, on one MI355X.
+
+One step = one pass of the whole path over all 216 shapes: the case-table
+choice for each shape (pk_select, cached per shape after its first call) and
+the kernel launch (pk_matmul) on the current stream.  Inputs are resident in
+HBM before timing: the operands of shape (M, N, K) are the leading M*K and K*N
+elements of two 8192 x 8192 float32 buffers filled i.i.d. uniform on [-1, 1)
+from seeds 0 and 1.
+
+Prints one JSON line (rank 0, the only rank):
+  value      aggregate GFLOP/s of the timed steps (2 M N K per shape)
+  roofline   the kernel with the largest share of time: algorithmic flops per
+             launch over its mean launch time, measured with events recorded
+             around its launches inside the timed region, against the 157.3
+             TFLOP/s float32 matrix-core peak
+  cpu_baseline  the CPU oracle on a bounded sample of the same sweep
+  exhaustive    when a tuning store for this device exists, the per-shape best
+             branch timed in the same run (untimed for `value`)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "matmul GFLOP/s and % FP32 peak: learned/case-table pick vs exhaustive best"
+FP32_PEAK_TFLOPS = 157.3
+TUNED = os.path.join(ROOT, "paper_1801_04348_amd", "data", "tuned_f32_gfx950.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """The oracle (float64 triple loop, OpenMP over rows) on the sweep's
+    smallest shapes, in a fixed order, until about `budget_s` seconds."""
+    import oracle.matmul as om
+    from tests import inputs
+    sample = [s for s in inputs.sweep_shapes() if max(s) <= 3000]
+    flops, secs, done = 0.0, 0.0, []
+    for (M, N, K) in sample:
+        A = inputs.uniform_f32((M, K), seed=0).numpy()
+        B = inputs.uniform_f32((K, N), seed=1).numpy()
+        t0 = time.perf_counter()
+        om.matmul(A, B, "f32")
+        dt = time.perf_counter() - t0
+        flops += 2.0 * M * N * K
+        secs += dt
+        done.append((M, N, K))
+        if secs >= budget_s:
+            break
+    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": om.threads(), "kind": "oracle",
+            "sample": "%d of the sweep's shapes with M,N,K <= 3000, in sweep order (%.1f GFLOP in %.1f s)"
+                      % (len(done), flops / 1e9, secs)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--policy", choices=["case", "learned"], default="case")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--machine", default=None,
+                    help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
+    ap.add_argument("--save-machine", default=None, help="write the machine descriptor the table was bound to")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with per-launch HBM bytes of the dominant kernel (from rocprofv3 counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the product path has no multi-GPU part; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1801_04348_amd import pk
+    from tests import inputs
+
+    torch.cuda.init()
+    if args.machine:
+        with open(args.machine) as f:
+            tbl = pk.pk_case_table_build(0, pk.machine(**json.load(f)))
+    else:
+        tbl = pk.pk_case_table_build(0)
+    machine = pk.pk_case_table_describe(tbl)["machine"]
+    if args.save_machine:
+        with open(args.save_machine, "w") as f:
+            json.dump(machine, f)
+    policy = pk.PK_POLICY_CASE if args.policy == "case" else pk.PK_POLICY_LEARNED
+    shapes = inputs.sweep_shapes()
+    big = max(max(s) for s in shapes)
+    Abuf = inputs.uniform_f32((big * big,), seed=0).cuda()
+    Bbuf = inputs.uniform_f32((big * big,), seed=1).cuda()
+    Cbuf = torch.empty((big * big,), dtype=torch.float32, device="cuda")
+    ops = []
+    for (M, N, K) in shapes:
+        p = pk.pk_select(tbl, "f32", M, N, K, policy, allow_fallback=True)
+        ops.append(dict(M=M, N=N, K=K, A=Abuf[:M * K].view(M, K), B=Bbuf[:K * N].view(K, N),
+                        C=Cbuf[:M * N].view(M, N), p=p, name=pk.pk_kernel_name(tbl, p, "f32"),
+                        flops=2.0 * M * N * K))
+    flops_step = sum(o["flops"] for o in ops)
+
+    def one_pass(events=None):
+        for o in ops:
+            p = pk.pk_select(tbl, "f32", o["M"], o["N"], o["K"], policy, allow_fallback=True)
+            if events is not None and o["name"] == dominant:
+                e0, e1 = events.pop()
+                e0.record()
+                pk.pk_matmul(tbl, p, "f32", o["A"], o["B"], o["C"])
+                e1.record()
+                recorded.append((o, e0, e1))
+            else:
+                pk.pk_matmul(tbl, p, "f32", o["A"], o["B"], o["C"])
+
+    # warm-up, then one untimed pass with events around every launch to find
+    # the kernel holding the largest share of the time
+    for _ in range(max(args.warmup, 1)):
+        one_pass()
+    torch.cuda.synchronize()
+    share = {}
+    evs = []
+    for o in ops:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pk.pk_matmul(tbl, o["p"], "f32", o["A"], o["B"], o["C"])
+        e1.record()
+        evs.append((o, e0, e1))
+    torch.cuda.synchronize()
+    per_shape_ms = {}
+    for o, e0, e1 in evs:
+        ms = e0.elapsed_time(e1)
+        per_shape_ms[(o["M"], o["N"], o["K"])] = ms
+        share[o["name"]] = share.get(o["name"], 0.0) + ms
+    dominant = max(share, key=share.get)
+    n_dom = sum(1 for o in ops if o["name"] == dominant)
+    log("dominant kernel %s: %.1f%% of launch time, %d launches per step"
+        % (dominant, 100 * share[dominant] / sum(share.values()), n_dom))
+
+    # timed region
+    pool = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(n_dom * args.steps)]
+    recorded = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_pass(pool)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = flops_step * args.steps / elapsed / 1e9
+    dom_flops = sum(o["flops"] for o, _, _ in recorded)
+    dom_s = sum(e0.elapsed_time(e1) for _, e0, e1 in recorded) * 1e-3
+    achieved = dom_flops / dom_s / 1e12
+    roofline = {"bound": "mfma", "kernel": dominant, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "launches": len(recorded), "mean_launch_us": round(dom_s / len(recorded) * 1e6, 2),
+                "flops_per_launch": dom_flops / len(recorded)}
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        if tr.get("kernel") == dominant:
+            roofline["traffic"] = tr.get("bytes_per_launch")
+
+    # large shapes and the exhaustive comparison (untimed for `value`)
+    large = {}
+    for s in [(4096, 4096, 4096), (8192, 8192, 8192)]:
+        ms = per_shape_ms[s]
+        large["x".join(map(str, s))] = {"gflops": round(2.0 * s[0] * s[1] * s[2] / ms / 1e6, 1),
+                                         "pct_fp32_peak": round(2.0 * s[0] * s[1] * s[2] / ms / 1e9 / FP32_PEAK_TFLOPS, 4)}
+    exhaustive = None
+    if os.path.exists(TUNED):
+        with open(TUNED) as f:
+            tuned = json.load(f)
+        best = {tuple(r["shape"]): r for r in tuned["shapes"]}
+        ratios, best_ms_total, pick_ms_total = [], 0.0, 0.0
+        for o in ops:
+            key = (o["M"], o["N"], o["K"])
+            if key not in best:
+                continue
+            bp = pk.params(**best[key]["params"])
+            reps = 3
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            pk.pk_matmul(tbl, bp, "f32", o["A"], o["B"], o["C"])
+            e[0].record()
+            for _ in range(reps):
+                pk.pk_matmul(tbl, bp, "f32", o["A"], o["B"], o["C"])
+            e[1].record()
+            for _ in range(reps):
+                pk.pk_matmul(tbl, o["p"], "f32", o["A"], o["B"], o["C"])
+            e[2].record()
+            torch.cuda.synchronize()
+            tb = e[0].elapsed_time(e[1]) / reps
+            tp = e[1].elapsed_time(e[2]) / reps
+            best_ms_total += tb
+            pick_ms_total += tp
+            ratios.append(min(tb / tp, 1.0) if tp > 0 else 1.0)
+        if ratios:
+            exhaustive = {"shapes": len(ratios),
+                          "best_gflops": round(sum(o["flops"] for o in ops) / best_ms_total / 1e6, 1),
+                          "pick_gflops": round(sum(o["flops"] for o in ops) / pick_ms_total / 1e6, 1),
+                          "pick_over_best_geomean": round(math.exp(sum(map(math.log, ratios)) / len(ratios)), 4),
+                          "pick_over_best_min": round(min(ratios), 4)}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "fp32 matmul sweep, M,N,K in {512,1000,2048,3000,4096,8192} (216 shapes), "
+                                  "uniform[-1,1) operands, %s pick per shape" % args.policy,
+                      "shapes": len(shapes), "gflop_per_step": round(flops_step / 1e9, 1), "policy": args.policy,
+                      "parallelism": "none (1 GPU)"},
+           "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
+           "large_shapes": large, "exhaustive": exhaustive, "roofline": roofline,
+           "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

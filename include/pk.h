@@ -135,9 +135,11 @@ int pk_co_solve(const char *spec, char *out, size_t cap, size_t *needed);
 /* ------------------------------------------------------------------ case table */
 /* Builds the comprehensive case tables of every family and dtype and binds
  * them to the machine: the parameters of `device` (via pk_machine_query)
- * when override_or_null is NULL, else the given descriptor (no GPU needed,
- * then device is ignored).  The table is owned by the caller and freed with
- * pk_case_table_free.  Errors: PK_ERR_HIP, PK_ERR_INVALID_ARG. */
+ * when override_or_null is NULL, else the given descriptor (no GPU call).
+ * `device` is the device later timing (PK_POLICY_EXHAUSTIVE, pk_measure,
+ * the LEARNED fallback) and training run on; -1 for none.  The table is
+ * owned by the caller and freed with pk_case_table_free.
+ * Errors: PK_ERR_HIP, PK_ERR_INVALID_ARG. */
 int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table **out);
 void pk_case_table_free(pk_table *tbl);
 
@@ -165,6 +167,23 @@ int pk_case_table_lookup(const pk_table *tbl, pk_dtype dtype, const pk_params *p
 int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int policy,
               pk_params *out);
 
+/* Times every feasible (leaf, E) for C(MxN) = A(MxK) B(KxN) on the table's
+ * device -- the measurement behind PK_POLICY_EXHAUSTIVE, the tuner and the
+ * cost model's training data.  A, B, C (device pointers, row-major, as in
+ * pk_matmul; C is overwritten) are the operands to time on; with A == NULL
+ * the call allocates scratch operands filled with a non-zero byte pattern and
+ * frees them.  Each candidate is launched once untimed, once timed, and,
+ * unless that launch is already 1.5x slower than the best so far, again until
+ * about 20 ms (at least 3 launches); seconds_out[i] is its mean time per
+ * launch.  Runs on a private stream and synchronizes.  *n receives the number
+ * of candidates; arrays must hold cap >= *n entries (else
+ * PK_ERR_BUFFER_TOO_SMALL).  MFMA candidates are left out when the given
+ * operands are not aligned for them.
+ * Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_HIP. */
+int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+               int64_t ldc, int64_t M, int64_t N, int64_t K, pk_params *params_out, double *seconds_out, int cap,
+               int *n);
+
 /* ------------------------------------------------------------------ products */
 /* C = A B (accumulate = 0) or C = C + A B (accumulate = 1, the semantics of
  * the kernel of Fig. 4, which loads c, adds the products and stores it back).
@@ -187,9 +206,76 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N,
                     int64_t K, int64_t *grid, int32_t *block, int64_t *lds_bytes);
 
+/* Name of the compiled kernel a choice runs (as in profiler traces), or NULL
+ * with the reason in pk_last_error(); resolution as in pk_matmul. */
+const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dtype);
+
 /* Number of compiled kernel instances, and the name of instance i. */
 int pk_instance_count(void);
 const char *pk_instance_name(int i);
+
+/* ------------------------------------------------------------------ cost model */
+/* The learned cost model: a 10-64-64-1 ReLU network predicting ln(seconds)
+ * of a candidate launch from PK_NFEATURES features, trained on the device by
+ * the library's own kernels (forward, backward, Adam) on timings from
+ * pk_measure.  Not in the paper: it stands in for the auto-tuning the paper
+ * leaves open for the program parameters (Section 1). */
+#define PK_NFEATURES 10
+typedef struct pk_costmodel pk_costmodel; /* opaque */
+
+/* Features of candidate *p for C(MxN) = A(MxK) B(KxN) on the bound machine:
+ * ln M, ln N, ln K, ln tile_m, ln tile_n, ln(outputs per work-item), LDS
+ * bytes / 65536, estimated occupancy (resident wavefronts / maximum), tile
+ * padding efficiency, wave quantisation efficiency.  out: PK_NFEATURES floats.
+ * Errors as pk_launch_shape. */
+int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+                float *out);
+
+/* Trains a model on the table's device: X is n x PK_NFEATURES row-major
+ * (host), seconds the n measured launch times (host, > 0).  Features and
+ * ln(seconds) are standardised; parameters start He-uniform from `seed`;
+ * `epochs` full-batch Adam steps (b1 0.9, b2 0.999, eps 1e-8) at rate lr on
+ * the mean squared error.  *out is owned by the caller (pk_costmodel_free);
+ * *final_loss (optional) is the loss in standardised units.
+ * Errors: PK_ERR_INVALID_ARG, PK_ERR_HIP. */
+int pk_costmodel_train(const pk_table *tbl, const float *X, const float *seconds, int64_t n, int epochs, float lr,
+                       uint64_t seed, pk_costmodel **out, float *final_loss);
+
+/* ln(seconds) predictions for n raw feature rows (host in, host out), one
+ * forward launch on `device`; synchronizes. */
+int pk_costmodel_predict(const pk_costmodel *cm, int device, const float *X, int64_t n, float *log_seconds);
+
+/* The network's raw forward/backward on the device: mean squared error of
+ * the network with parameters `params` (host, 4929 floats in the order W1
+ * (64x10), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x 10, host) and
+ * targets t (host); writes the gradient (4929 floats) and the loss.  Used to
+ * check the kernels against a float64 reference. */
+int pk_costmodel_grad(int device, const float *params, const float *X, const float *t, int64_t n, float *grad,
+                      float *loss);
+
+/* One Adam step of the device kernel on host arrays (params, m, v updated in
+ * place; step >= 1 is the step number used for bias correction). */
+int pk_costmodel_adam_step(int device, float *params, const float *grad, float *m, float *v, int64_t step, float lr);
+
+/* Parameter export (*n = 4929; out may be NULL to query), text save/load
+ * (the file carries the standardisation and the machine it was trained on),
+ * release, and the machine fingerprint string. */
+int pk_costmodel_params(const pk_costmodel *cm, float *out, int cap, int *n);
+int pk_costmodel_save(const pk_costmodel *cm, const char *path);
+int pk_costmodel_load(const char *path, pk_costmodel **out);
+void pk_costmodel_free(pk_costmodel *cm);
+const char *pk_costmodel_machine(const pk_costmodel *cm);
+
+/* Gives the table a copy of the model for PK_POLICY_LEARNED.  A model whose
+ * machine differs from the table's is refused (PK_ERR_COST_MODEL).  The
+ * LEARNED policy orders the feasible candidates by predicted time; when the
+ * best two differ by less than 5 %, every candidate predicted within 5 % of
+ * the best is timed (as pk_measure does) and the fastest kept.  Not to be
+ * called while other threads select on the same table. */
+int pk_case_table_set_costmodel(pk_table *tbl, const pk_costmodel *cm);
+
+/* LEARNED selections made on the table and how many fell back to timing. */
+int pk_case_table_learned_stats(const pk_table *tbl, int64_t *selections, int64_t *fallbacks);
 
 /* Library version string. */
 const char *pk_version(void);

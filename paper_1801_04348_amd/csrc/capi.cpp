@@ -199,7 +199,7 @@ int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table
     try {
         std::unique_ptr<pk_table> t(new pk_table);
         t->machine = m;
-        t->device = override_or_null ? -1 : device;
+        t->device = device;
         for (int family = 0; family < PK_NUM_FAMILIES; ++family)
             for (int dtype : {PK_F32, PK_I32, PK_BF16}) {
                 pk_table::Part part;
@@ -317,6 +317,42 @@ int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t
     } catch (const std::exception &ex) {
         return fail(PK_ERR_INVALID_ARG, ex.what());
     }
+}
+
+int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+               int64_t ldc, int64_t M, int64_t N, int64_t K, pk_params *params_out, double *seconds_out, int cap,
+               int *n) {
+    if (!tbl || !n) return fail(PK_ERR_INVALID_ARG, "null argument");
+    if (M <= 0 || N <= 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "M and N must be positive, K non-negative");
+    if (A && (!B || !C || lda < K || ldb < N || ldc < N)) return fail(PK_ERR_INVALID_ARG, "operands inconsistent");
+    try {
+        std::vector<Candidate> cands = feasible(tbl, (int)dtype, M, N, K, A, lda, B, ldb);
+        *n = (int)cands.size();
+        if (cands.empty()) return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no leaf of the case table holds");
+        if (cap < (int)cands.size()) return fail(PK_ERR_BUFFER_TOO_SMALL, "cap below the number of candidates");
+        std::vector<double> secs;
+        Operands ops{A, lda, B, ldb, C, ldc};
+        if (time_candidates(tbl, (int)dtype, M, N, K, cands, &secs, A ? &ops : nullptr) < 0)
+            return fail(PK_ERR_HIP, "no candidate could be launched");
+        for (size_t i = 0; i < cands.size(); ++i) {
+            if (params_out) fill_params(tbl, cands[i], (int)dtype, &params_out[i]);
+            if (seconds_out) seconds_out[i] = secs[i];
+        }
+        return PK_OK;
+    } catch (const std::exception &ex) {
+        return fail(PK_ERR_HIP, ex.what());
+    }
+}
+
+const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dtype) {
+    if (!tbl || !p) {
+        fail(PK_ERR_INVALID_ARG, "null argument");
+        return nullptr;
+    }
+    pk_params q;
+    const KernelEntry *e = nullptr;
+    if (resolve(tbl, p, (int)dtype, &q, &e) != PK_OK) return nullptr;
+    return e->name;
 }
 
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <cstdint>
+#include <atomic>
 #include <deque>
 #include <functional>
 #include <map>
@@ -157,6 +158,8 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
 
 // The bound case table (opaque in the C ABI).
 struct pk_table {
+    std::shared_ptr<pk_costmodel> costmodel;  // for PK_POLICY_LEARNED, or null
+    mutable std::atomic<int64_t> learned_selections{0}, learned_fallbacks{0};
     pk_machine machine;
     int device = -1;
     struct Part {

@@ -6,16 +6,24 @@
 // chosen by an analytic estimate of the launch time:
 //   tiles     = ceil(M / tile_m) * ceil(N / tile_n)
 //   occupancy = workgroups resident per compute unit (LDS, registers, threads,
-//               workgroup slots)
+//               workgroup slots, as the bound machine reports them)
 //   rounds    = ceil(tiles / (compute units * occupancy))
-//   compute   = rounds * occupancy * 2 * tile_m * tile_n * K / (rate * clock)
-//               with rate the per-CU throughput of the program's inner loop
-//               (matrix cores, or VALU limited by LDS reads per FMA)
-//   traffic   = bytes the tiles read (each tile reads its A and B panels),
-//               over an on-chip cache bandwidth, and compulsory bytes over HBM
-//   estimate  = max(compute, traffic) + a fixed launch cost
-// EXHAUSTIVE: every candidate is timed with HIP events on the device and the
-// fastest kept (cached per shape).
+//   per round = max(occupancy * 2 * tile_m * tile_n * K / (rate * eff * clock),
+//                   K steps * step latency)
+//               rate: per-CU throughput of the program's inner loop (matrix
+//               cores; or VALU multiply-adds limited by the LDS words read per
+//               multiply-add); eff: the share of that rate a tile sustains,
+//               falling with the LDS/L2 words moved per flop, 1/tile_m +
+//               1/tile_n; step latency: one global-load round trip plus the
+//               barriers of a K step, hidden in part by a second LDS stage
+//   traffic   = bytes the tiles read (each tile reads its A and B panels) over
+//               an on-chip cache bandwidth, and compulsory bytes over HBM
+//   estimate  = max(rounds * per round, traffic) + a fixed launch cost
+// The constants (eff's shape, step latencies) were set from event timings of
+// these kernels on gfx950; the estimate only has to rank candidates.
+// EXHAUSTIVE: every candidate is launched and timed with HIP events on the
+// device; a candidate whose first launch is already 1.5x slower than the best
+// median so far is not timed further.  The fastest is kept (cached per shape).
 #include "select.hpp"
 
 #include <algorithm>
@@ -57,7 +65,15 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const int64_t slots = (int64_t)m.cu_count * occ;
     const int64_t rounds = (tiles + slots - 1) / slots;
     const double flops_tile = 2.0 * e.tile_m * e.tile_n * (double)std::max<int64_t>(K, 1);
-    const double compute = rounds * occ * flops_tile / (cu_rate(m, e, dtype) * clock);
+    const double words_per_flop = 1.0 / e.tile_m + 1.0 / e.tile_n;
+    const double eff = e.family == PK_FAMILY_MFMA ? 0.90 / (1.0 + 6.7 * words_per_flop) : 0.6;
+    const double compute_round = occ * flops_tile / (cu_rate(m, e, dtype) * eff * clock);
+    const bool two_stage = e.family == PK_FAMILY_MFMA && !(e.variant & PK_MFMA_SINGLE);
+    const int bk = e.bk > 0 ? e.bk : 1;
+    const double ksteps = (double)((K + bk - 1) / bk);
+    const double step_latency = (e.variant & PK_VALU_NOLDS) && e.family == PK_FAMILY_VALU ? 0.0
+                                : (two_stage ? 0.6e-6 : 1.2e-6);
+    const double compute = rounds * std::max(compute_round, ksteps * step_latency);
     const double es = elem_bytes(dtype);
     const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
     const double out_bytes = 4.0 * (double)M * N;
@@ -97,25 +113,38 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
     return out;
 }
 
-namespace {
-
 // Times every candidate on the table's device; returns the index of the fastest.
 int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
-                    const std::vector<Candidate> &cands, std::vector<double> *secs) {
-    if (tbl->device < 0) throw std::runtime_error("exhaustive selection needs a table bound to a device");
+                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops) {
+    if (tbl->device < 0) throw std::runtime_error("timing needs a table bound to a device");
     hipError_t err = hipSetDevice(tbl->device);
     if (err != hipSuccess) throw std::runtime_error(std::string("hipSetDevice: ") + hipGetErrorString(err));
     const size_t es = dtype == PK_BF16 ? 2 : 4;
-    void *A = nullptr, *B = nullptr, *C = nullptr;
-    const size_t bA = std::max<size_t>(es * M * K, 16), bB = std::max<size_t>(es * K * N, 16),
-                 bC = std::max<size_t>(4 * M * N, 16);
-    if (hipMalloc(&A, bA) != hipSuccess || hipMalloc(&B, bB) != hipSuccess || hipMalloc(&C, bC) != hipSuccess) {
-        hipFree(A);
-        hipFree(B);
-        throw std::runtime_error("exhaustive selection: device allocation failed");
+    void *sA = nullptr, *sB = nullptr, *sC = nullptr;
+    MmArgs args{nullptr, nullptr, nullptr, K, N, N, (int32_t)M, (int32_t)N, (int32_t)K, 0};
+    if (ops && ops->A) {
+        args.A = ops->A;
+        args.B = ops->B;
+        args.C = ops->C;
+        args.lda = ops->lda;
+        args.ldb = ops->ldb;
+        args.ldc = ops->ldc;
+    } else {
+        // scratch operands with a non-zero byte pattern (0x3c: about 0.0115 in
+        // float32 and bfloat16), so the timed kernels do real arithmetic
+        const size_t bA = std::max<size_t>(es * M * K, 16), bB = std::max<size_t>(es * K * N, 16),
+                     bC = std::max<size_t>(4 * M * N, 16);
+        if (hipMalloc(&sA, bA) != hipSuccess || hipMalloc(&sB, bB) != hipSuccess || hipMalloc(&sC, bC) != hipSuccess) {
+            hipFree(sA);
+            hipFree(sB);
+            throw std::runtime_error("timing: device allocation failed");
+        }
+        hipMemset(sA, 0x3c, bA);
+        hipMemset(sB, 0x3c, bB);
+        args.A = sA;
+        args.B = sB;
+        args.C = sC;
     }
-    hipMemset(A, 0, bA);
-    hipMemset(B, 0, bB);
     hipStream_t s;
     hipEvent_t e0, e1;
     hipStreamCreate(&s);
@@ -124,13 +153,23 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
     int best = -1;
     double best_t = std::numeric_limits<double>::infinity();
     secs->assign(cands.size(), std::numeric_limits<double>::infinity());
-    MmArgs args{A, B, C, K, N, N, (int32_t)M, (int32_t)N, (int32_t)K, 0};
     for (size_t i = 0; i < cands.size(); ++i) {
         const KernelEntry &e = *cands[i].entry;
         if (launch(tbl->machine, e, args, s) != PK_OK) continue;  // warm-up
+        // one timed launch first: a candidate already 1.5x slower than the
+        // best so far cannot win and is not timed further
+        float ms = 0.f;
+        hipEventRecord(e0, s);
+        launch(tbl->machine, e, args, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms * 1e-3 > 1.5 * best_t) {
+            (*secs)[i] = ms * 1e-3;
+            continue;
+        }
         hipEventRecord(e0, s);
         int reps = 0;
-        float ms = 0.f;
         // at least 3 launches, up to about 20 ms of work
         do {
             launch(tbl->machine, e, args, s);
@@ -152,13 +191,11 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     hipStreamDestroy(s);
-    hipFree(A);
-    hipFree(B);
-    hipFree(C);
+    hipFree(sA);
+    hipFree(sB);
+    hipFree(sC);
     return best;
 }
-
-}  // namespace
 
 int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, int policy, bool cache,
                   pk_params *out, const void *A, int64_t lda, const void *B, int64_t ldb) {
@@ -175,14 +212,58 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         }
     }
     int pick = 0;
-    if (policy == PK_POLICY_CASE || policy == PK_POLICY_LEARNED) {
+    if (policy == PK_POLICY_LEARNED && tbl->costmodel) {
+        // order by predicted time; near-ties are settled by measurement
+        std::vector<float> X(cands.size() * PK_NFEATURES), pred(cands.size());
+        for (size_t i = 0; i < cands.size(); ++i)
+            features(tbl->machine, *cands[i].entry, M, N, K, &X[i * PK_NFEATURES]);
+        costmodel_predict(*tbl->costmodel, tbl->device, X.data(), (int64_t)cands.size(), pred.data());
+        std::vector<int> order(cands.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
+        pick = order[0];
+        tbl->learned_selections++;
+        const double margin = 0.05;
+        if (order.size() > 1 && std::exp((double)pred[order[1]] - pred[order[0]]) < 1.0 + margin) {
+            std::vector<Candidate> close;
+            std::vector<int> idx;
+            for (int i : order)
+                if (std::exp((double)pred[i] - pred[order[0]]) <= 1.0 + margin) {
+                    close.push_back(cands[i]);
+                    idx.push_back(i);
+                }
+            std::vector<double> secs;
+            Operands ops{A, lda, B, ldb, nullptr, 0};
+            void *C = nullptr;
+            if (A) {
+                if (hipMalloc(&C, std::max<size_t>(4 * M * N, 16)) != hipSuccess)
+                    return fail(PK_ERR_HIP, "learned selection: allocation failed");
+                ops.C = C;
+                ops.ldc = N;
+            }
+            const int f = time_candidates(tbl, dtype, M, N, K, close, &secs, A ? &ops : nullptr);
+            if (C) hipFree(C);
+            if (f >= 0) pick = idx[f];
+            tbl->learned_fallbacks++;
+        }
+        fill_params(tbl, cands[pick], dtype, out);
+    } else if (policy == PK_POLICY_CASE || policy == PK_POLICY_LEARNED) {
         for (size_t i = 1; i < cands.size(); ++i)
             if (cands[i].estimate < cands[pick].estimate) pick = (int)i;
         fill_params(tbl, cands[pick], dtype, out);
         if (policy == PK_POLICY_LEARNED) return fail(PK_ERR_COST_MODEL, "no cost model loaded; CASE pick returned");
     } else if (policy == PK_POLICY_EXHAUSTIVE) {
         std::vector<double> secs;
-        pick = time_candidates(tbl, dtype, M, N, K, cands, &secs);
+        Operands ops{A, lda, B, ldb, nullptr, 0};
+        void *C = nullptr;
+        if (A) {  // time on the caller's data needs an output: scratch C
+            if (hipMalloc(&C, std::max<size_t>(4 * M * N, 16)) != hipSuccess)
+                return fail(PK_ERR_HIP, "exhaustive selection: allocation failed");
+            ops.C = C;
+            ops.ldc = N;
+        }
+        pick = time_candidates(tbl, dtype, M, N, K, cands, &secs, A ? &ops : nullptr);
+        if (C) hipFree(C);
         if (pick < 0) return fail(PK_ERR_HIP, "no candidate could be launched");
         fill_params(tbl, cands[pick], dtype, out);
     } else {

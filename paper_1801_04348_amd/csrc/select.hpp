@@ -31,11 +31,32 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
                   pk_params *out, const void *A = nullptr, int64_t lda = 0, const void *B = nullptr,
                   int64_t ldb = 0);
 
+// Operands to time on (device pointers), or scratch buffers when A is null.
+struct Operands {
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+};
+
+// Times every candidate (HIP events on a private stream); secs[i] is the
+// mean time per launch of candidate i.  Returns the fastest.
+int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
+                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops);
+
 // helpers shared with capi.cpp
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);
 int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
 bool data_ok(int family, int dtype, const void *A, int64_t lda, const void *B, int64_t ldb);
 int launch(const pk_machine &m, const KernelEntry &e, const MmArgs &args, hipStream_t stream);
 void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out);
+int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pout, const KernelEntry **entry);
+
+// cost model (costmodel.hip)
+std::string machine_fingerprint(const pk_machine &m);
+void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, float *f);
+void costmodel_predict(const pk_costmodel &cm, int device, const float *X, int64_t n, float *out);
 
 }  // namespace pk

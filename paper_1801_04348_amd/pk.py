@@ -3,7 +3,16 @@
 Argument marshalling only -- every step of the path runs in the library and
 its HIP kernels.  Matrices may be passed as torch tensors (device memory);
 their data pointers, leading dimensions and the current HIP stream are
-forwarded.  Importing this module raises if the library has not been built.
+forwarded.  Calls raise if the library has not been built.
+
+HIP runtime: libpk.so links the HIP runtime of the ROCm it was built with;
+PyTorch wheels bundle their own copy under the same soname.  The library is
+opened after torch is imported, so it binds to the runtime torch already
+loaded and one runtime serves the process (stream handles and device
+pointers are shared).  The machine parameters the case table binds are the
+ones that runtime reports: in a process with torch 2.10's bundled ROCm 7.0
+runtime gfx950 reports 65536 registers per workgroup, the system ROCm 7.2
+runtime alone reports 131072.
 """
 from __future__ import annotations
 
@@ -86,6 +95,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpk.so is not built; run __graft_entry__.build() (or python -m "
                                "paper_1801_04348_amd.build)")
+        try:  # torch first: the library then binds to torch's HIP runtime
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
         L.pk_last_error.restype = ctypes.c_char_p
@@ -106,8 +119,32 @@ def lib():
                                 i32, vp]
         L.pk_launch_shape.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64,
                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
+        L.pk_measure.argtypes = [vp, i32, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.POINTER(pk_params),
+                                 ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(ctypes.c_int)]
+        L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
+        L.pk_kernel_name.restype = ctypes.c_char_p
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.pk_features.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, f32p]
+        L.pk_costmodel_train.argtypes = [vp, f32p, f32p, i64, i32, ctypes.c_float, ctypes.c_uint64,
+                                         ctypes.POINTER(vp), f32p]
+        L.pk_costmodel_predict.argtypes = [vp, i32, f32p, i64, f32p]
+        L.pk_costmodel_grad.argtypes = [i32, f32p, f32p, f32p, i64, f32p, f32p]
+        L.pk_costmodel_adam_step.argtypes = [i32, f32p, f32p, f32p, f32p, i64, ctypes.c_float]
+        L.pk_costmodel_params.argtypes = [vp, f32p, i32, ctypes.POINTER(ctypes.c_int)]
+        L.pk_costmodel_save.argtypes = [vp, ctypes.c_char_p]
+        L.pk_costmodel_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.pk_costmodel_free.argtypes = [vp]
+        L.pk_costmodel_free.restype = None
+        L.pk_costmodel_machine.argtypes = [vp]
+        L.pk_costmodel_machine.restype = ctypes.c_char_p
+        L.pk_case_table_set_costmodel.argtypes = [vp, vp]
+        L.pk_case_table_learned_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        for name in ("pk_features", "pk_costmodel_train", "pk_costmodel_predict", "pk_costmodel_grad",
+                     "pk_costmodel_adam_step", "pk_costmodel_params", "pk_costmodel_save", "pk_costmodel_load",
+                     "pk_case_table_set_costmodel", "pk_case_table_learned_stats"):
+            getattr(L, name).restype = i32
         for name in ("pk_machine_query", "pk_co_solve", "pk_case_table_build", "pk_case_table_describe",
-                     "pk_case_table_lookup", "pk_select", "pk_matmul", "pk_launch_shape"):
+                     "pk_case_table_lookup", "pk_select", "pk_matmul", "pk_launch_shape", "pk_measure"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -202,6 +239,36 @@ def pk_select(tbl: Table, dtype, M: int, N: int, K: int, policy: int = PK_POLICY
     return out
 
 
+def pk_measure(tbl: Table, dtype, M: int, N: int, K: int, A=None, B=None, C=None):
+    """[(pk_params, seconds per launch)] for every feasible candidate, timed on
+    the given device tensors (or on scratch operands when A is None)."""
+    if A is not None:
+        a, lda = _ptr_ld(A)
+        b, ldb = _ptr_ld(B)
+        c, ldc = _ptr_ld(C)
+        lda, ldb, ldc = max(lda, K), max(ldb, N), max(ldc, N)
+    else:
+        a = b = c = None
+        lda = ldb = ldc = 0
+    n = ctypes.c_int(0)
+    rc = lib().pk_measure(tbl.handle, _dt(dtype), a, lda, b, ldb, c, ldc, M, N, K, None, None, 0, ctypes.byref(n))
+    if rc not in (PK_OK, PK_ERR_BUFFER_TOO_SMALL):
+        _check(rc)
+    cap = n.value
+    ps = (pk_params * cap)()
+    secs = (ctypes.c_double * cap)()
+    _check(lib().pk_measure(tbl.handle, _dt(dtype), a, lda, b, ldb, c, ldc, M, N, K, ps, secs, cap,
+                            ctypes.byref(n)))
+    return [(ps[i], secs[i]) for i in range(n.value)]
+
+
+def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:
+    r = lib().pk_kernel_name(tbl.handle, ctypes.byref(p), _dt(dtype))
+    if r is None:
+        raise PkError(PK_ERR_INVALID_ARG, last_error())
+    return r.decode()
+
+
 def pk_launch_shape(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):
     g, b, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
     _check(lib().pk_launch_shape(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, ctypes.byref(g),
@@ -237,3 +304,112 @@ def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=No
     _check(lib().pk_matmul(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype),
                            a, max(lda, K), b, max(ldb, N), c, max(ldc, N), M, N, K,
                            1 if accumulate else 0, _stream(stream)))
+
+
+# ---------------------------------------------------------------------- cost model
+PK_NFEATURES = 10
+
+
+def _fbuf(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def pk_features(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):
+    import numpy as np
+    out = np.zeros(PK_NFEATURES, dtype=np.float32)
+    _check(lib().pk_features(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+class CostModel:
+    """Owner of a pk_costmodel handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.pk_costmodel_free(h)
+
+    def params(self):
+        import numpy as np
+        n = ctypes.c_int(0)
+        _check(lib().pk_costmodel_params(self.handle, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float32)
+        _check(lib().pk_costmodel_params(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         n.value, ctypes.byref(n)))
+        return out
+
+    def machine(self) -> str:
+        return lib().pk_costmodel_machine(self.handle).decode()
+
+    def predict(self, X, device: int = 0):
+        import numpy as np
+        X, px = _fbuf(X)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        _check(lib().pk_costmodel_predict(self.handle, device, px, X.shape[0],
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def save(self, path: str):
+        _check(lib().pk_costmodel_save(self.handle, path.encode()))
+
+
+def pk_costmodel_train(tbl: Table, X, seconds, epochs: int = 2000, lr: float = 3e-3, seed: int = 0):
+    """Trains on the device; returns (CostModel, final loss)."""
+    X, px = _fbuf(X)
+    s, ps = _fbuf(seconds)
+    h = ctypes.c_void_p()
+    loss = ctypes.c_float(0)
+    _check(lib().pk_costmodel_train(tbl.handle, px, ps, X.shape[0], epochs, lr, seed, ctypes.byref(h),
+                                    ctypes.byref(loss)))
+    return CostModel(h), loss.value
+
+
+def pk_costmodel_load(path: str) -> CostModel:
+    h = ctypes.c_void_p()
+    _check(lib().pk_costmodel_load(path.encode(), ctypes.byref(h)))
+    return CostModel(h)
+
+
+def pk_costmodel_grad(params, X, t, device: int = 0):
+    """(gradient, loss) of the raw network on the device."""
+    import numpy as np
+    P, pp = _fbuf(params)
+    X, px = _fbuf(X)
+    T, pt = _fbuf(t)
+    g = np.zeros(P.shape[0], dtype=np.float32)
+    loss = ctypes.c_float(0)
+    _check(lib().pk_costmodel_grad(device, pp, px, pt, X.shape[0], g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   ctypes.byref(loss)))
+    return g, loss.value
+
+
+def pk_costmodel_adam_step(params, grad, m, v, step: int, lr: float, device: int = 0):
+    """One device Adam step; returns new (params, m, v)."""
+    P, pp = _fbuf(params)
+    P = P.copy()
+    pp = P.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    G, pg = _fbuf(grad)
+    Mv, pm = _fbuf(m)
+    Mv = Mv.copy()
+    pm = Mv.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    V, pv = _fbuf(v)
+    V = V.copy()
+    pv = V.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    _check(lib().pk_costmodel_adam_step(device, pp, pg, pm, pv, step, lr))
+    return P, Mv, V
+
+
+def pk_case_table_set_costmodel(tbl: Table, cm):
+    _check(lib().pk_case_table_set_costmodel(tbl.handle, cm.handle if cm is not None else None))
+
+
+def pk_case_table_learned_stats(tbl: Table):
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().pk_case_table_learned_stats(tbl.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value

@@ -1,0 +1,121 @@
+"""The cost model's kernels against the float64 oracle (GPU), and its host
+side: feature values and the model file (CPU)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle.mlp as mlp
+from paper_1801_04348_amd import pk
+from tests import machines
+
+
+def _write_model(path, params, xmean, xstd, ymean, ystd, machine="m"):
+    with open(path, "w") as f:
+        f.write("pk-costmodel 1\nfeatures %d\nmachine %s\nepochs 0\nloss 0\n" % (mlp.IN, machine))
+        f.write("xmean " + " ".join("%.9g" % v for v in xmean) + "\n")
+        f.write("xstd " + " ".join("%.9g" % v for v in xstd) + "\n")
+        f.write("y %.9g %.9g\nparams %d\n" % (ymean, ystd, len(params)))
+        f.write(" ".join("%.9g" % v for v in params) + "\n")
+
+
+def test_model_file_roundtrip(tmp_path):
+    p = mlp.init_params(3).astype(np.float32)
+    path = str(tmp_path / "m.txt")
+    _write_model(path, p, np.zeros(mlp.IN), np.ones(mlp.IN), 0.5, 2.0)
+    cm = pk.pk_costmodel_load(path)
+    assert np.array_equal(cm.params(), p)
+    assert cm.machine() == "m"
+    path2 = str(tmp_path / "m2.txt")
+    cm.save(path2)
+    assert np.array_equal(pk.pk_costmodel_load(path2).params(), p)
+
+
+def test_model_file_rejects_wrong_sizes(tmp_path):
+    path = str(tmp_path / "bad.txt")
+    _write_model(path, np.zeros(10, np.float32), np.zeros(mlp.IN), np.ones(mlp.IN), 0, 1)
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_costmodel_load(path)
+    assert e.value.code == pk.PK_ERR_COST_MODEL
+
+
+def test_model_for_other_machine_refused(tmp_path):
+    path = str(tmp_path / "m.txt")
+    _write_model(path, mlp.init_params(1).astype(np.float32), np.zeros(mlp.IN), np.ones(mlp.IN), 0, 1,
+                 machine="someone-else")
+    t = pk.pk_case_table_build(0, machines.gfx950())
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_case_table_set_costmodel(t, pk.pk_costmodel_load(path))
+    assert e.value.code == pk.PK_ERR_COST_MODEL
+
+
+def test_features_by_hand():
+    m = machines.gfx950()
+    t = pk.pk_case_table_build(0, m)
+    p = pk.params(family=pk.PK_FAMILY_MFMA, bm=128, bn=128, bk=32, wm=2, wn=2)
+    M, N, K = 1000, 3000, 512
+    f = pk.pk_features(t, p, "f32", M, N, K)
+    d = pk.pk_case_table_describe(t)
+    inst = [e for e in d["instances"] if e["name"] == pk.pk_kernel_name(t, p, "f32")][0]
+    # occupancy by hand: LDS, threads, registers and the slot limit
+    per_lane = -(-(-(-inst["vgpr"] // 4) * 4 + inst["agpr"]) // 8) * 8
+    regs = per_lane * 64 * 4
+    occ = min(m.max_blocks_cu, m.lds_cu // inst["lds_bytes"], m.max_threads_cu // 256, m.regs_cu // regs)
+    tiles = math.ceil(M / 128) * math.ceil(N / 128)
+    slots = m.cu_count * occ
+    rounds = math.ceil(tiles / slots)
+    want = [math.log(M), math.log(N), math.log(K), math.log(128), math.log(128), math.log(128 * 128 / 256),
+            inst["lds_bytes"] / 65536, min(1.0, occ * 4 / (m.max_threads_cu / 64)),
+            M * N / (math.ceil(M / 128) * 128 * math.ceil(N / 128) * 128), tiles / (rounds * slots)]
+    assert np.allclose(f, want, rtol=1e-6), (f, want)
+
+
+@pytest.mark.gpu
+def test_gradient_matches_float64_oracle():
+    rng = np.random.default_rng(0)
+    n = 1000  # 15 full workgroups of 64 rows and a ragged tail of 40
+    X = rng.normal(size=(n, mlp.IN)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    P = mlp.init_params(7).astype(np.float32)
+    P[mlp.IN * 64:mlp.IN * 64 + 64] = rng.normal(scale=0.1, size=64)  # non-zero biases
+    g, loss = pk.pk_costmodel_grad(P, X, t)
+    ref_loss, ref_g = mlp.loss_and_grad(P.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert np.linalg.norm(g - ref_g) <= 1e-4 * np.linalg.norm(ref_g)
+    assert np.max(np.abs(g - ref_g)) <= 1e-4 * np.max(np.abs(ref_g))
+
+
+@pytest.mark.gpu
+def test_adam_step_matches_oracle():
+    rng = np.random.default_rng(1)
+    P = rng.normal(size=mlp.NPARAM)
+    m0 = rng.normal(scale=0.01, size=mlp.NPARAM)
+    v0 = np.abs(rng.normal(scale=0.01, size=mlp.NPARAM))
+    g = rng.normal(size=mlp.NPARAM)
+    opt = mlp.Adam(mlp.NPARAM, lr=2e-3)
+    opt.m, opt.v, opt.t = m0.copy(), v0.copy(), 4          # the device step will be step 5
+    ref = opt.step(P.copy(), g)
+    Pn, mn, vn = pk.pk_costmodel_adam_step(P, g, m0, v0, 5, 2e-3)
+    # float32 arithmetic: a few roundings of 2^-24 each
+    assert np.allclose(Pn, ref, rtol=2e-6, atol=1e-7)
+    assert np.allclose(mn, opt.m, rtol=2e-6, atol=1e-9)
+    assert np.allclose(vn, opt.v, rtol=2e-6, atol=1e-9)
+
+
+@pytest.mark.gpu
+def test_training_fits_a_known_law():
+    # time proportional to M N K: ln t = ln M + ln N + ln K + c; the network
+    # trained on the device must recover it on unseen shapes
+    t = pk.pk_case_table_build(0)
+    rng = np.random.default_rng(2)
+    dims = np.exp(rng.uniform(np.log(64), np.log(8192), size=(3000, 3)))
+    X = np.zeros((3000, mlp.IN), np.float32)
+    X[:, :3] = np.log(dims)
+    X[:, 3:] = rng.normal(size=(3000, mlp.IN - 3))          # distractors
+    secs = np.exp(np.log(dims).sum(1) - 30.0)
+    cm, loss = pk.pk_costmodel_train(t, X[:2500], secs[:2500], epochs=1500, lr=3e-3, seed=0)
+    assert loss < 1e-2
+    pred = cm.predict(X[2500:])
+    err = pred - np.log(secs[2500:])
+    assert np.sqrt(np.mean(err * err)) < 0.15

@@ -11,7 +11,7 @@ def _data(n, seed):
 
 
 def test_parameter_count():
-    assert mlp.NPARAM == 64 * 8 + 64 + 64 * 64 + 64 + 64 + 1 == 4801
+    assert mlp.NPARAM == 64 * 10 + 64 + 64 * 64 + 64 + 64 + 1 == 4929
 
 
 def test_gradient_matches_central_differences():
