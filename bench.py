@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "matmul GFLOP/s and % FP32 peak: learned/case-table pick vs exhaustive best"
 FP32_PEAK_TFLOPS = 157.3
 TUNED = os.path.join(ROOT, "paper_1801_04348_amd", "data", "tuned_f32_gfx950.json")
+PROFILES = os.path.join(ROOT, "profiles")
+COPY_BYTES = 256 << 20
 
 
 def log(*a):
@@ -73,8 +75,8 @@ def main():
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
     ap.add_argument("--save-machine", default=None, help="write the machine descriptor the table was bound to")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with per-launch HBM bytes of the dominant kernel (from rocprofv3 counters)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a 256 MiB device copy three times (known bytes, for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the product path has no multi-GPU part; run with --gpus 1",
@@ -102,6 +104,13 @@ def main():
     Abuf = inputs.uniform_f32((big * big,), seed=0).cuda()
     Bbuf = inputs.uniform_f32((big * big,), seed=1).cuda()
     Cbuf = torch.empty((big * big,), dtype=torch.float32, device="cuda")
+    if args.calibrate_copy:
+        src_t = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            torch.add(src_t, 0.0, out=dst_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
     ops = []
     for (M, N, K) in shapes:
         p = pk.pk_select(tbl, "f32", M, N, K, policy, allow_fallback=True)
@@ -159,17 +168,24 @@ def main():
     elapsed = time.perf_counter() - t0
     value = flops_step * args.steps / elapsed / 1e9
     dom_flops = sum(o["flops"] for o, _, _ in recorded)
+    dom_bytes = sum(4.0 * (o["M"] * o["K"] + o["K"] * o["N"] + o["M"] * o["N"]) for o, _, _ in recorded)
     dom_s = sum(e0.elapsed_time(e1) for _, e0, e1 in recorded) * 1e-3
     achieved = dom_flops / dom_s / 1e12
     roofline = {"bound": "mfma", "kernel": dominant, "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
                 "launches": len(recorded), "mean_launch_us": round(dom_s / len(recorded) * 1e6, 2),
-                "flops_per_launch": dom_flops / len(recorded)}
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
+                "flops_per_launch": dom_flops / len(recorded),
+                "algorithmic_bytes_per_launch": dom_bytes / len(recorded)}
+    # HBM bytes per launch of this kernel from the counter passes, if they
+    # were taken on the current kernel source (see paper_1801_04348_amd/traffic.py)
+    from paper_1801_04348_amd import traffic as trf
+    tr_path = os.path.join(PROFILES, "traffic_%s.json" % dominant)
+    if os.path.exists(tr_path):
+        with open(tr_path) as f:
             tr = json.load(f)
-        if tr.get("kernel") == dominant:
-            roofline["traffic"] = tr.get("bytes_per_launch")
+        if tr.get("kernel") == dominant and tr.get("source_sha256") == trf.kernel_source_hash():
+            roofline["traffic"] = tr["bytes_per_launch"]
+            roofline["traffic_over_algorithmic"] = round(tr["bytes_per_launch"] / roofline["algorithmic_bytes_per_launch"], 3)
 
     # large shapes and the exhaustive comparison (untimed for `value`)
     large = {}

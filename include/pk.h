@@ -86,8 +86,11 @@ typedef struct {
 #define PK_VALU_GRAN 1
 #define PK_VALU_NOLDS 2
 /* Strategy bits of the MFMA family:
- * PK_MFMA_SINGLE - one LDS stage instead of two (halves the LDS tile footprint) */
+ * PK_MFMA_SINGLE - one LDS stage instead of two (halves the LDS tile footprint)
+ * PK_MFMA_GROUPED marks the persistent grouped instances of the same programs
+ * (not a strategy of the case table; set only in instance descriptions) */
 #define PK_MFMA_SINGLE 1
+#define PK_MFMA_GROUPED 2
 
 /* A leaf choice together with its program parameters E.
  *   family  - PK_FAMILY_*
@@ -200,6 +203,46 @@ int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, 
 int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype,
               const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
               int64_t M, int64_t N, int64_t K, int accumulate, void *hip_stream);
+
+/* ------------------------------------------------------------------ many products */
+/* A plan for G independent products C_g = [C_g +] A_g B_g (f32 or bf16 ->
+ * f32), run as one persistent launch per tile configuration: every workgroup
+ * strides over the configuration's tiles of all its products.  Sizes and
+ * pointer arrays are host arrays (device pointers inside), all of length G;
+ * products with M or N = 0 are skipped.  per_group_or_null gives each
+ * product's MFMA leaf/parameters (resolved as in pk_matmul); NULL chooses
+ * per product with `policy` (PK_POLICY_CASE, or PK_POLICY_LEARNED when the
+ * table has a cost model) among the MFMA candidates that have grouped
+ * instances.  Rows that are not aligned for the 16-byte loads are read with
+ * element loads.  The plan copies its descriptors to the device when created
+ * (allocating and synchronizing then); running it allocates nothing and does
+ * not synchronize, so it may be captured in a HIP graph.  Pointers must stay
+ * valid while the plan is used.  Errors: PK_ERR_INVALID_ARG,
+ * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_NOT_INSTANTIATED,
+ * PK_ERR_HIP. */
+typedef struct pk_grouped_plan pk_grouped_plan;
+int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
+                           const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
+                           const int64_t *ldb, void *const *C, const int64_t *ldc,
+                           const pk_params *per_group_or_null, int policy, int accumulate,
+                           pk_grouped_plan **out);
+/* Queues the plan's launches on hip_stream. */
+int pk_grouped_plan_run(const pk_grouped_plan *plan, void *hip_stream);
+/* Captures the plan's launches once into a HIP graph owned by the plan;
+ * pk_grouped_plan_replay launches that graph on hip_stream. */
+int pk_grouped_plan_capture(pk_grouped_plan *plan);
+int pk_grouped_plan_replay(const pk_grouped_plan *plan, void *hip_stream);
+/* Launch count, total tiles, and (cap >= G) the choice made per product. */
+int pk_grouped_plan_info(const pk_grouped_plan *plan, int32_t *launches, int64_t *total_tiles, pk_params *chosen,
+                         int32_t cap);
+void pk_grouped_plan_destroy(pk_grouped_plan *plan);
+
+/* One-shot form: creates a plan (CASE choice when per_group_or_null is NULL),
+ * runs it on hip_stream, synchronizes the stream and destroys the plan. */
+int pk_matmul_batched(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
+                      const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
+                      const int64_t *ldb, void *const *C, const int64_t *ldc, const pk_params *per_group_or_null,
+                      void *hip_stream);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */

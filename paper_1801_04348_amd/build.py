@@ -37,7 +37,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC,
           "-Wno-unused-command-line-argument"]
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
-HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp"]
+HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp"]
 DEVICE_SOURCES = ["costmodel.hip"]
 
 F32, I32, BF16 = 0, 1, 2
@@ -46,6 +46,7 @@ DT_CTYPE = {F32: "float", I32: "int32_t"}
 FAM_VALU, FAM_MFMA = 0, 1
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
+MFMA_GROUPED = 2
 
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
@@ -93,6 +94,19 @@ def instances():
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
+    # persistent grouped instances of the MFMA programs up to 128 x 128
+    gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
+    for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):
+        for (bm, bn, bk, wm, wn) in cfgs:
+            if bm > 128 or bn > 128:
+                continue
+            for stages in (2, 1):
+                name = "pk_grouped_%s_%dx%dx%d_w%dx%d_st%d" % (DT_NAME[dt], bm, bn, bk, wm, wn, stages)
+                body = "pkk::%s<%d, %d, %d, %d, %d, %d>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages)
+                entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE),
+                             dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
+                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, grouped=True)
+                out.append(("grouped_%s" % DT_NAME[dt], name, body, entry))
     return out
 
 
@@ -112,8 +126,9 @@ def generate():
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
                  "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"', ""]
         for name, body, entry in items:
-            lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(pkk::MmArgs a) { %s }'
-                         % (entry["threads"], name, body))
+            arg = "pkk::GroupArgs g" if entry.get("grouped") else "pkk::MmArgs a"
+            lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'
+                         % (entry["threads"], name, arg, body))
         lines.append("")
         lines.append("static const pkk::KernelEntry entries[] = {")
         for name, body, entry in items:

@@ -1,0 +1,130 @@
+"""Training and evaluation of the learned cost model from timing stores.
+
+    python -m paper_1801_04348_amd.costmodel train --store S1.jsonl [--store S2.jsonl] --out MODEL.txt
+    python -m paper_1801_04348_amd.costmodel eval --model MODEL.txt --store HELDOUT.jsonl [--json OUT.json]
+
+train: one row per (shape, candidate) of the stores (written by tune.py on
+this device): the library's features of the candidate (pk_features) and its
+measured seconds; the network is trained on the device by the library
+(pk_costmodel_train) and saved with its standardisation and the machine it
+was trained on.
+
+eval: for every shape of a held-out store, the LEARNED choice as pk_select
+makes it -- the candidate with the least predicted time, except that when the
+best two predictions are within 5 % every candidate predicted within 5 % of
+the best is measured and the fastest kept; the measurement used is the
+store's own -- and the CASE choice, each scored by its measured time against
+the best measured candidate:  ratio = t_best / t_pick = GF_pick / GF_best.
+Reports the geometric mean, median, 10th percentile and worst ratio and the
+fallback rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MARGIN = 0.05
+
+
+def load_store(paths, fingerprint):
+    recs = []
+    for p in paths:
+        with open(p) as f:
+            for line in f:
+                r = json.loads(line)
+                if r["machine"] == fingerprint:
+                    recs.append(r)
+    return recs
+
+
+def fingerprint_of(pk, tbl):
+    m = pk.pk_case_table_describe(tbl)["machine"]
+    return {k: m[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_threads_block", "clock_khz")}
+
+
+def feature_rows(pk, tbl, rec):
+    import numpy as np
+    M, N, K = rec["shape"]
+    X = np.stack([pk.pk_features(tbl, pk.params(**c["params"]), rec["dtype"], M, N, K) for c in rec["candidates"]])
+    t = np.array([c["seconds"] for c in rec["candidates"]], dtype=np.float64)
+    return X, t
+
+
+def stats(ratios):
+    import numpy as np
+    r = np.sort(np.asarray(ratios))
+    return {"shapes": int(r.size), "geomean": float(np.exp(np.mean(np.log(r)))), "median": float(np.median(r)),
+            "p10": float(np.percentile(r, 10)), "worst": float(r[0])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--store", action="append", required=True)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--model", default=None)
+    ap.add_argument("--epochs", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch  # noqa: F401  (one HIP runtime: torch's, see pk.py)
+
+    from paper_1801_04348_amd import pk
+
+    tbl = pk.pk_case_table_build(0)
+    fp = fingerprint_of(pk, tbl)
+    recs = load_store(args.store, fp)
+    if not recs:
+        sys.exit("no timing records for this machine in %s" % args.store)
+
+    if args.cmd == "train":
+        Xs, ts = zip(*(feature_rows(pk, tbl, r) for r in recs))
+        X = np.concatenate(Xs).astype(np.float32)
+        t = np.concatenate(ts)
+        cm, loss = pk.pk_costmodel_train(tbl, X, t, epochs=args.epochs, lr=args.lr, seed=args.seed)
+        pred = cm.predict(X)
+        rmse = float(np.sqrt(np.mean((pred - np.log(t)) ** 2)))
+        cm.save(args.out)
+        print(json.dumps({"rows": int(X.shape[0]), "shapes": len(recs), "epochs": args.epochs, "lr": args.lr,
+                          "loss_standardised": loss, "rmse_ln_seconds": rmse, "model": args.out}), flush=True)
+        return
+
+    cm = pk.pk_costmodel_load(args.model)
+    pk.pk_case_table_set_costmodel(tbl, cm)
+    learned, case, fallbacks = [], [], 0
+    for r in recs:
+        M, N, K = r["shape"]
+        X, t = feature_rows(pk, tbl, r)
+        pred = cm.predict(X)
+        order = np.argsort(pred, kind="stable")
+        pick = int(order[0])
+        if len(order) > 1 and math.exp(pred[order[1]] - pred[order[0]]) < 1.0 + MARGIN:
+            close = [int(i) for i in order if math.exp(pred[i] - pred[order[0]]) <= 1.0 + MARGIN]
+            pick = min(close, key=lambda i: t[i])
+            fallbacks += 1
+        best = float(t.min())
+        learned.append(best / t[pick])
+        cp = pk.pk_select(tbl, r["dtype"], M, N, K, pk.PK_POLICY_CASE).as_dict()
+        tc = [c["seconds"] for c in r["candidates"] if c["params"] == cp]
+        case.append(best / tc[0] if tc else float("nan"))
+    out = {"learned": stats(learned), "case": stats([c for c in case if c == c]),
+           "fallback_rate": fallbacks / len(recs), "margin": MARGIN, "model": args.model}
+    out["learned_over_case_geomean"] = out["learned"]["geomean"] / out["case"]["geomean"]
+    print(json.dumps(out), flush=True)
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

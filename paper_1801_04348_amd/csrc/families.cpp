@@ -225,7 +225,7 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
         if (variant & PK_VALU_GRAN) q[2] = 1;
         kind = variant & PK_VALU_NOLDS;
     } else {
-        kind = variant & PK_MFMA_SINGLE;
+        kind = variant & (PK_MFMA_SINGLE | PK_MFMA_GROUPED);
     }
     for (const auto &e : registry()) {
         if (e.family != family || e.dtype != dtype || e.variant != kind) continue;

@@ -1,0 +1,293 @@
+// Many independent products in one persistent launch per tile configuration.
+//
+// A plan fixes, once, everything a grouped launch needs: for every product its
+// leaf and program parameters (given, or chosen by the table's selection
+// policy among the MFMA points that have grouped instances), its descriptor
+// (pointers, leading dimensions, sizes, whether rows are aligned for the wide
+// loads, first global tile index), and a tile -> product map.  Products are
+// partitioned by tile configuration; each part is one persistent launch whose
+// workgroups stride over that part's tiles.  Descriptors and maps are staged in
+// pinned host memory and copied to the device when the plan is created, so
+// running a plan allocates nothing and does not synchronise: it can be
+// captured in a HIP graph, and pk_grouped_plan_capture does that itself.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+
+#include "pk_internal.hpp"
+#include "select.hpp"
+
+using pkk::GroupArgs;
+using pkk::GroupDesc;
+
+struct pk_grouped_plan {
+    int dtype = 0;
+    int device = -1;
+    int accumulate = 0;
+    struct Launch {
+        const pk::KernelEntry *entry = nullptr;
+        int64_t first_desc = 0, ndesc = 0;     // range in the descriptor array
+        int64_t first_tile = 0, total_tiles = 0;  // range in the tile map
+        int64_t grid = 0;
+    };
+    std::vector<Launch> launches;
+    std::vector<pk_params> chosen;  // per product, in the caller's order
+    void *host = nullptr;           // pinned staging copy
+    void *dev = nullptr;            // descriptors, then tile maps
+    size_t bytes = 0;
+    int64_t ndesc = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~pk_grouped_plan() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (dev) hipFree(dev);
+        if (host) hipHostFree(host);
+    }
+};
+
+namespace pk {
+
+// MFMA points with grouped instances, for the dtype
+static bool grouped_instance(int dtype, int variant, const std::vector<int64_t> &pt, const KernelEntry **e) {
+    *e = find_instance(PK_FAMILY_MFMA, variant | PK_MFMA_GROUPED, dtype, pt);
+    return *e != nullptr;
+}
+
+static bool aligned_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
+    return data_ok(PK_FAMILY_MFMA, dtype, A, lda, B, ldb);
+}
+
+}  // namespace pk
+
+using namespace pk;
+
+extern "C" {
+
+int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
+                           const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
+                           const int64_t *ldb, void *const *C, const int64_t *ldc,
+                           const pk_params *per_group_or_null, int policy, int accumulate,
+                           pk_grouped_plan **out) {
+    if (!tbl || !out || G < 0 || (G > 0 && (!M || !N || !K || !A || !lda || !B || !ldb || !C || !ldc)))
+        return fail(PK_ERR_INVALID_ARG, "null argument or negative group count");
+    if (dtype != PK_F32 && dtype != PK_BF16) return fail(PK_ERR_UNSUPPORTED_DTYPE, "grouped products: f32 or bf16");
+    if (tbl->device < 0) return fail(PK_ERR_INVALID_ARG, "grouped plans need a table bound to a device");
+    *out = nullptr;
+    try {
+        std::unique_ptr<pk_grouped_plan> plan(new pk_grouped_plan);
+        plan->dtype = (int)dtype;
+        plan->device = tbl->device;
+        plan->accumulate = accumulate ? 1 : 0;
+        const pk_table::Part *part = tbl->part(PK_FAMILY_MFMA, (int)dtype);
+        // choose per product: candidates are the feasible MFMA (leaf, E) pairs
+        // with grouped instances; the policy ranks them (one batched
+        // prediction for all products under LEARNED)
+        std::map<const KernelEntry *, std::vector<int>> by_entry;
+        plan->chosen.assign(G, pk_params{});
+        std::vector<std::vector<Candidate>> okc(G);
+        for (int g = 0; g < G; ++g) {
+            if (M[g] < 0 || N[g] < 0 || K[g] < 0 || M[g] > 0x7fffffff || N[g] > 0x7fffffff || K[g] > 0x7fffffff)
+                return fail(PK_ERR_INVALID_ARG, "bad size in product " + std::to_string(g));
+            if (M[g] == 0 || N[g] == 0) continue;
+            if (!C[g] || ldc[g] < N[g] || (K[g] > 0 && (!A[g] || !B[g] || lda[g] < K[g] || ldb[g] < N[g])))
+                return fail(PK_ERR_INVALID_ARG, "bad operands in product " + std::to_string(g));
+            if (per_group_or_null) continue;
+            const KernelEntry *ge = nullptr;
+            for (const auto &c : feasible(tbl, (int)dtype, M[g], N[g], K[g]))
+                if (c.family == PK_FAMILY_MFMA &&
+                    grouped_instance((int)dtype, c.variant, part->fam.points[c.point], &ge))
+                    okc[g].push_back(c);
+            if (okc[g].empty())
+                return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no grouped program fits product " + std::to_string(g));
+        }
+        std::vector<float> pred;
+        const bool learned = !per_group_or_null && policy == PK_POLICY_LEARNED && tbl->costmodel;
+        if (learned) {
+            std::vector<float> X;
+            for (int g = 0; g < G; ++g)
+                for (const auto &c : okc[g]) {
+                    X.resize(X.size() + PK_NFEATURES);
+                    features(tbl->machine, *c.entry, M[g], N[g], K[g], &X[X.size() - PK_NFEATURES]);
+                }
+            pred.resize(X.size() / PK_NFEATURES);
+            costmodel_predict(*tbl->costmodel, tbl->device, X.data(), (int64_t)pred.size(), pred.data());
+        }
+        size_t row = 0;
+        for (int g = 0; g < G; ++g) {
+            if (M[g] == 0 || N[g] == 0) continue;
+            pk_params p;
+            if (per_group_or_null) {
+                p = per_group_or_null[g];
+                if (p.family != PK_FAMILY_MFMA)
+                    return fail(PK_ERR_UNSUPPORTED_DTYPE, "grouped launches run MFMA programs only");
+                pk_params q;
+                const KernelEntry *e0 = nullptr;
+                int rc = resolve(tbl, &p, (int)dtype, &q, &e0);
+                if (rc != PK_OK) return rc;
+                p = q;
+            } else {
+                const auto &ok = okc[g];
+                int pick = 0;
+                for (size_t i = 1; i < ok.size(); ++i) {
+                    const bool better = learned ? pred[row + i] < pred[row + pick] : ok[i].estimate < ok[pick].estimate;
+                    if (better) pick = (int)i;
+                }
+                row += ok.size();
+                fill_params(tbl, ok[pick], (int)dtype, &p);
+            }
+            std::vector<int64_t> pt;
+            params_point(PK_FAMILY_MFMA, p, &pt);
+            const KernelEntry *e = nullptr;
+            if (!grouped_instance((int)dtype, p.variant, pt, &e))
+                return fail(PK_ERR_NOT_INSTANTIATED, "no grouped instance for product " + std::to_string(g));
+            plan->chosen[g] = p;
+            by_entry[e].push_back(g);
+        }
+        // descriptors and tile maps, one contiguous block per launch
+        std::vector<GroupDesc> descs;
+        std::vector<int32_t> tmap;
+        for (auto &kv : by_entry) {
+            const KernelEntry *e = kv.first;
+            pk_grouped_plan::Launch L;
+            L.entry = e;
+            L.first_desc = (int64_t)descs.size();
+            L.first_tile = (int64_t)tmap.size();
+            int64_t tiles = 0;
+            for (int g : kv.second) {
+                GroupDesc d;
+                std::memset(&d, 0, sizeof d);
+                d.A = A[g];
+                d.B = B[g];
+                d.C = C[g];
+                d.lda = lda[g];
+                d.ldb = ldb[g];
+                d.ldc = ldc[g];
+                d.M = (int32_t)M[g];
+                d.N = (int32_t)N[g];
+                d.K = (int32_t)K[g];
+                d.vec = aligned_rows((int)dtype, A[g], lda[g], B[g], ldb[g]) ? 1 : 0;
+                d.tile_start = tiles;
+                d.tiles_n = (int32_t)((N[g] + e->tile_n - 1) / e->tile_n);
+                const int64_t t = ((M[g] + e->tile_m - 1) / e->tile_m) * d.tiles_n;
+                const int32_t local = (int32_t)(descs.size() - L.first_desc);
+                for (int64_t i = 0; i < t; ++i) tmap.push_back(local);
+                tiles += t;
+                descs.push_back(d);
+            }
+            L.ndesc = (int64_t)descs.size() - L.first_desc;
+            L.total_tiles = tiles;
+            L.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)tbl->machine.cu_count *
+                                                                       blocks_per_cu(tbl->machine, *e)));
+            plan->launches.push_back(L);
+        }
+        plan->ndesc = (int64_t)descs.size();
+        const size_t dbytes = descs.size() * sizeof(GroupDesc);
+        plan->bytes = dbytes + tmap.size() * sizeof(int32_t);
+        if (plan->bytes > 0) {
+            hipError_t err = hipSetDevice(tbl->device);
+            if (err == hipSuccess) err = hipHostMalloc(&plan->host, plan->bytes, hipHostMallocDefault);
+            if (err == hipSuccess) err = hipMalloc(&plan->dev, plan->bytes);
+            if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("grouped plan: ") + hipGetErrorString(err));
+            std::memcpy(plan->host, descs.data(), dbytes);
+            std::memcpy((char *)plan->host + dbytes, tmap.data(), tmap.size() * sizeof(int32_t));
+            err = hipMemcpy(plan->dev, plan->host, plan->bytes, hipMemcpyHostToDevice);
+            if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("grouped plan upload: ") + hipGetErrorString(err));
+        }
+        *out = plan.release();
+        return PK_OK;
+    } catch (const std::exception &ex) {
+        return fail(PK_ERR_INVALID_ARG, ex.what());
+    }
+}
+
+int pk_grouped_plan_run(const pk_grouped_plan *plan, void *hip_stream) {
+    if (!plan) return fail(PK_ERR_INVALID_ARG, "null plan");
+    const size_t dbytes = (size_t)plan->ndesc * sizeof(GroupDesc);
+    for (const auto &L : plan->launches) {
+        GroupArgs a;
+        a.descs = (const GroupDesc *)plan->dev + L.first_desc;
+        a.tile_group = (const int32_t *)((const char *)plan->dev + dbytes) + L.first_tile;
+        a.total_tiles = L.total_tiles;
+        a.accumulate = plan->accumulate;
+        a.pad = 0;
+        void *kargs[] = {&a};
+        hipError_t err = hipLaunchKernel(L.entry->fn, dim3((unsigned)L.grid), dim3((unsigned)L.entry->threads), kargs,
+                                         0, (hipStream_t)hip_stream);
+        if (err != hipSuccess)
+            return fail(PK_ERR_HIP, std::string("hipLaunchKernel(") + L.entry->name + "): " + hipGetErrorString(err));
+    }
+    return PK_OK;
+}
+
+int pk_grouped_plan_capture(pk_grouped_plan *plan) {
+    if (!plan) return fail(PK_ERR_INVALID_ARG, "null plan");
+    if (plan->exec) return PK_OK;
+    hipStream_t s;
+    hipError_t err = hipSetDevice(plan->device);
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("capture stream: ") + hipGetErrorString(err));
+    err = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    int rc = PK_OK;
+    if (err == hipSuccess) rc = pk_grouped_plan_run(plan, s);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    hipStreamDestroy(s);
+    if (err != hipSuccess || e2 != hipSuccess || rc != PK_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc != PK_OK ? rc : fail(PK_ERR_HIP, std::string("capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    err = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(PK_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err));
+    }
+    plan->graph = g;
+    return PK_OK;
+}
+
+int pk_grouped_plan_replay(const pk_grouped_plan *plan, void *hip_stream) {
+    if (!plan || !plan->exec) return fail(PK_ERR_INVALID_ARG, "plan not captured");
+    hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(err));
+    return PK_OK;
+}
+
+int pk_grouped_plan_info(const pk_grouped_plan *plan, int32_t *launches, int64_t *total_tiles, pk_params *chosen,
+                         int32_t cap) {
+    if (!plan) return fail(PK_ERR_INVALID_ARG, "null plan");
+    if (launches) *launches = (int32_t)plan->launches.size();
+    if (total_tiles) {
+        int64_t t = 0;
+        for (const auto &L : plan->launches) t += L.total_tiles;
+        *total_tiles = t;
+    }
+    if (chosen) {
+        if (cap < (int32_t)plan->chosen.size()) return fail(PK_ERR_BUFFER_TOO_SMALL, "cap below the product count");
+        std::copy(plan->chosen.begin(), plan->chosen.end(), chosen);
+    }
+    return PK_OK;
+}
+
+void pk_grouped_plan_destroy(pk_grouped_plan *plan) { delete plan; }
+
+int pk_matmul_batched(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
+                      const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
+                      const int64_t *ldb, void *const *C, const int64_t *ldc, const pk_params *per_group_or_null,
+                      void *hip_stream) {
+    pk_grouped_plan *plan = nullptr;
+    int rc = pk_grouped_plan_create(tbl, dtype, G, M, N, K, A, lda, B, ldb, C, ldc, per_group_or_null,
+                                    PK_POLICY_CASE, 0, &plan);
+    if (rc != PK_OK) return rc;
+    rc = pk_grouped_plan_run(plan, hip_stream);
+    hipError_t err = hipStreamSynchronize((hipStream_t)hip_stream);
+    pk_grouped_plan_destroy(plan);
+    if (rc != PK_OK) return rc;
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(err));
+    return PK_OK;
+}
+
+}  // extern "C"

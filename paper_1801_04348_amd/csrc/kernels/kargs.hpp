@@ -17,6 +17,28 @@ struct MmArgs {
     int32_t accumulate;
 };
 
+// One product of a grouped launch.
+struct GroupDesc {
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t vec;         // rows aligned for the wide loads
+    int64_t tile_start;  // first global tile index of this product
+    int32_t tiles_n;     // tiles along N
+    int32_t pad;
+};
+
+// Arguments of a grouped kernel: descriptors and the tile -> product map.
+struct GroupArgs {
+    const GroupDesc *descs;
+    const int32_t *tile_group;
+    int64_t total_tiles;
+    int32_t accumulate;
+    int32_t pad;
+};
+
 // One compiled kernel instance, as listed by the generated registry.
 struct KernelEntry {
     const char *name;

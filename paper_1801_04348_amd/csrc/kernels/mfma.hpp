@@ -66,8 +66,11 @@ __device__ __forceinline__ void tile_of(int64_t b, int tiles_m, int tiles_n, int
 }
 
 // ------------------------------------------------------------------ float32
+// One BM x BN output tile at (row0, col0).  `vec`: the rows of A and B are
+// 16-byte aligned, so interior tiles may use 16-byte loads.  The caller
+// synchronises the workgroup before reusing the LDS for another tile.
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
-__device__ __forceinline__ void mfma_f32(const MmArgs &a) {
+__device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
@@ -91,10 +94,6 @@ __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
     const int wm = wave / WN, wn = wave % WN;
     const int r = lane & 31, h = lane >> 5;
 
-    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-    int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
-    const int row0 = tm * BM, col0 = tn * BN;
     const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
 
     f32x16 acc[TM][TN];
@@ -113,7 +112,7 @@ __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
             const int gr = row0 + rr, gc = k0 + c4;
-            if (kfull && (interior || gr < M)) {
+            if (vec && kfull && (interior || gr < M)) {
                 ra[u] = *reinterpret_cast<const f32x4 *>(A + (int64_t)gr * a.lda + gc);
             } else {
 #pragma unroll
@@ -126,7 +125,7 @@ __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
             const int f = tid + u * NT;
             const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
             const int gr = k0 + rr, gc = col0 + c4;
-            if (gr < K && (interior || gc + 4 <= N)) {
+            if (vec && gr < K && (interior || gc + 4 <= N)) {
                 rb[u] = *reinterpret_cast<const f32x4 *>(B + (int64_t)gr * a.ldb + gc);
             } else {
 #pragma unroll
@@ -214,8 +213,9 @@ __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
 }
 
 // ------------------------------------------------------------------ bfloat16
+// bfloat16 tile; `vec`: A rows 16-byte aligned and B rows 4-byte aligned.
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
-__device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
+__device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
@@ -239,10 +239,6 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
     const int wm = wave / WN, wn = wave % WN;
     const int r = lane & 31, h = lane >> 5;
 
-    const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-    int tm, tn;
-    tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
-    const int row0 = tm * BM, col0 = tn * BN;
     const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
 
     f32x16 acc[TM][TN];
@@ -262,7 +258,7 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
             const int gr = row0 + rr, gc = k0 + c8;
-            if (kfull && (interior || gr < M)) {
+            if (vec && kfull && (interior || gr < M)) {
                 ra[u] = *reinterpret_cast<const u16x8 *>(A + (int64_t)gr * a.lda + gc);
             } else {
 #pragma unroll
@@ -278,7 +274,7 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int gr = k0 + kr + e;
-                if (gr < K && (interior || gc + 2 <= N)) {
+                if (vec && gr < K && (interior || gc + 2 <= N)) {
                     rb[u][e] = *reinterpret_cast<const unsigned int *>(B + (int64_t)gr * a.ldb + gc);
                 } else {
                     unsigned int lo = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : 0u;
@@ -366,6 +362,49 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
                 }
             }
         }
+}
+
+// ------------------------------------------------------------------ single product
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void mfma_f32(const MmArgs &a) {
+    int tm, tn;
+    tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, true);
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
+    int tm, tn;
+    tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, true);
+}
+
+// ------------------------------------------------------------------ grouped (persistent)
+// Many independent products in one launch: workgroups stride over the global
+// tile index; tile t belongs to group tile_group[t] and is tile
+// t - tile_start of that group, numbered row-major over its tiles.
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
+    for (int64_t t = blockIdx.x; t < g.total_tiles; t += gridDim.x) {
+        const GroupDesc &d = g.descs[g.tile_group[t]];
+        const int64_t local = t - d.tile_start;
+        const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate};
+        __syncthreads();  // the previous tile's LDS reads are done
+        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
+    }
+}
+
+template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+__device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
+    for (int64_t t = blockIdx.x; t < g.total_tiles; t += gridDim.x) {
+        const GroupDesc &d = g.descs[g.tile_group[t]];
+        const int64_t local = t - d.tile_start;
+        const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate};
+        __syncthreads();
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
+    }
 }
 
 }  // namespace pkk

@@ -413,3 +413,96 @@ def pk_case_table_learned_stats(tbl: Table):
     a, b = ctypes.c_int64(0), ctypes.c_int64(0)
     _check(lib().pk_case_table_learned_stats(tbl.handle, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+# ---------------------------------------------------------------------- many products
+def _grouped_arrays(As, Bs, Cs):
+    G = len(As)
+    if not (len(Bs) == len(Cs) == G):
+        raise ValueError("As, Bs, Cs must have the same length")
+    I64 = ctypes.c_int64 * G
+    P = ctypes.c_void_p * G
+    M, N, K, lda, ldb, ldc = I64(), I64(), I64(), I64(), I64(), I64()
+    a, b, c = P(), P(), P()
+    for g, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        m, k = A.shape
+        k2, n = B.shape
+        if k2 != k or tuple(C.shape) != (m, n):
+            raise ValueError("shape mismatch in product %d" % g)
+        M[g], N[g], K[g] = m, n, k
+        pa, la = _ptr_ld(A)
+        pb, lb = _ptr_ld(B)
+        pc, lc = _ptr_ld(C)
+        a[g], b[g], c[g] = pa.value, pb.value, pc.value
+        lda[g], ldb[g], ldc[g] = max(la, k), max(lb, n), max(lc, n)
+    return G, (M, N, K, a, lda, b, ldb, c, ldc)
+
+
+def _grouped_sigs(L):
+    vp, i64p, i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int
+    arrs = [i64p, i64p, i64p, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), i64p]
+    if getattr(L, "_grouped_sigs", False):
+        return
+    L.pk_grouped_plan_create.argtypes = [vp, i32, ctypes.c_int32] + arrs + [ctypes.POINTER(pk_params), i32, i32,
+                                                                              ctypes.POINTER(vp)]
+    L.pk_grouped_plan_run.argtypes = [vp, vp]
+    L.pk_grouped_plan_capture.argtypes = [vp]
+    L.pk_grouped_plan_replay.argtypes = [vp, vp]
+    L.pk_grouped_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(pk_params), ctypes.c_int32]
+    L.pk_grouped_plan_destroy.argtypes = [vp]
+    L.pk_grouped_plan_destroy.restype = None
+    L.pk_matmul_batched.argtypes = [vp, i32, ctypes.c_int32] + arrs + [ctypes.POINTER(pk_params), vp]
+    for n in ("pk_grouped_plan_create", "pk_grouped_plan_run", "pk_grouped_plan_capture", "pk_grouped_plan_replay",
+              "pk_grouped_plan_info", "pk_matmul_batched"):
+        getattr(L, n).restype = i32
+    L._grouped_sigs = True
+
+
+class GroupedPlan:
+    """Owner of a pk_grouped_plan handle (keeps the operand tensors alive)."""
+
+    def __init__(self, handle, G, keep):
+        self.handle, self.G, self._keep = handle, G, keep
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h and _lib is not None:
+            _lib.pk_grouped_plan_destroy(h)
+
+    def run(self, stream=None):
+        _check(lib().pk_grouped_plan_run(self.handle, _stream(stream)))
+
+    def capture(self):
+        _check(lib().pk_grouped_plan_capture(self.handle))
+
+    def replay(self, stream=None):
+        _check(lib().pk_grouped_plan_replay(self.handle, _stream(stream)))
+
+    def info(self):
+        n, t = ctypes.c_int32(0), ctypes.c_int64(0)
+        chosen = (pk_params * max(self.G, 1))()
+        _check(lib().pk_grouped_plan_info(self.handle, ctypes.byref(n), ctypes.byref(t), chosen, self.G))
+        return n.value, t.value, [chosen[i] for i in range(self.G)]
+
+
+def pk_grouped_plan_create(tbl: Table, dtype, As, Bs, Cs, params=None, policy: int = PK_POLICY_CASE,
+                           accumulate: bool = False) -> GroupedPlan:
+    L = lib()
+    _grouped_sigs(L)
+    G, arrs = _grouped_arrays(As, Bs, Cs)
+    ps = None
+    if params is not None:
+        ps = (pk_params * G)(*params)
+    h = ctypes.c_void_p()
+    _check(L.pk_grouped_plan_create(tbl.handle, _dt(dtype), G, *arrs, ps, policy, 1 if accumulate else 0,
+                                    ctypes.byref(h)))
+    return GroupedPlan(h, G, (As, Bs, Cs, arrs))
+
+
+def pk_matmul_batched(tbl: Table, dtype, As, Bs, Cs, params=None, stream=None):
+    L = lib()
+    _grouped_sigs(L)
+    G, arrs = _grouped_arrays(As, Bs, Cs)
+    ps = (pk_params * G)(*params) if params is not None else None
+    _check(L.pk_matmul_batched(tbl.handle, _dt(dtype), G, *arrs, ps, _stream(stream)))

@@ -1,0 +1,85 @@
+"""HBM traffic per launch of the benchmark's dominant kernel from rocprofv3
+counters, calibrated by a copy of known size.
+
+Two counter passes over the benchmark command, one counter each (each pass a
+run of its own), with the calibration copy switched on:
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o fetch -- \\
+        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --machine M.json --calibrate-copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o write -- \\
+        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --machine M.json --calibrate-copy
+    python3 paper_1801_04348_amd/traffic.py --fetch D1 --write D2 --kernel NAME --out profiles/traffic_NAME.json
+
+The calibration copy (a float32 add of zero over 256 MiB: reads 256 MiB and
+writes 256 MiB) gives, per counter, factor = known bytes / counter bytes; the
+kernel's bytes per launch are its mean counter value over all its launches
+(in KiB per dispatch) times that factor.  The result records a hash of the
+kernel sources so the benchmark ignores it once the kernels change.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 256 << 20
+KERNEL_SOURCES = ("csrc/kernels/mfma.hpp", "csrc/kernels/valu.hpp", "csrc/kernels/kargs.hpp")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_per_dispatch(d, counter):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % d)
+    per = {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") != counter:
+                    continue
+                key = (fn, int(r.get("Dispatch_Id", 0)), r.get("Kernel_Name", ""))
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return [(k[2], v) for k, v in sorted(per.items())]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    out = {"kernel": args.kernel, "source_sha256": kernel_source_hash(), "copy_bytes": COPY_BYTES}
+    total = 0.0
+    for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        rows = counter_per_dispatch(d, counter)
+        copies = sorted(v for name, v in rows if not name.startswith("pk_") and v * 1024 > COPY_BYTES / 4)
+        kern = [v for name, v in rows if name == args.kernel]
+        if not copies or not kern:
+            raise SystemExit("missing calibration copies or %s dispatches for %s" % (args.kernel, counter))
+        copy_kib = copies[len(copies) // 2]
+        factor = COPY_BYTES / (copy_kib * 1024.0)
+        b = sum(kern) / len(kern) * 1024.0 * factor
+        out[counter] = {"copy_kib": copy_kib, "factor": factor, "launches": len(kern),
+                        "kernel_kib_per_launch": sum(kern) / len(kern), "bytes_per_launch": b}
+        total += b
+    out["bytes_per_launch"] = total
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

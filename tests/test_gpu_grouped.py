@@ -1,0 +1,164 @@
+"""Grouped persistent launches (many independent products) through the C ABI:
+each product against the oracle, bit-exact against the single-product launch
+of the same program, graph replays, sentinels, and the 4096-product size."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.matmul as om
+from paper_1801_04348_amd import pk
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def table():
+    return pk.pk_case_table_build(0)
+
+
+def rel_fro(c, ref):
+    c = np.asarray(c, dtype=np.float64)
+    den = np.linalg.norm(ref)
+    num = np.linalg.norm(c - ref)
+    return 0.0 if num == 0 else num / den
+
+
+def make_groups(G, seed, dtype, aligned_every=1, lo=16, hi=512):
+    """Products with sizes round(exp(U(ln lo, ln hi))); every `aligned_every`-th
+    product gets leading dimensions padded to 8 elements (16-byte rows), the
+    others are packed tightly (rows generally unaligned)."""
+    dims = inputs.group_dims(G, seed, lo, hi)
+    host, dev = [], []
+    for g, (M, N, K) in enumerate(dims):
+        M, N, K = int(M), int(N), int(K)
+        a32 = inputs.uniform_f32((M, K), seed=seed * 100003 + 2 * g)
+        b32 = inputs.uniform_f32((K, N), seed=seed * 100003 + 2 * g + 1)
+        a = inputs.bf16_bits(a32) if dtype == "bf16" else a32
+        b = inputs.bf16_bits(b32) if dtype == "bf16" else b32
+        pad = (g % aligned_every == 0)
+        if pad:
+            Kp, Np = (K + 7) // 8 * 8, (N + 7) // 8 * 8
+            ad = torch.zeros((M, Kp), dtype=a.dtype, device="cuda")
+            bd = torch.zeros((K, Np), dtype=b.dtype, device="cuda")
+            ad[:, :K] = a.cuda()
+            bd[:, :N] = b.cuda()
+            ad, bd = ad[:, :K], bd[:, :N]
+        else:
+            ad, bd = a.cuda(), b.cuda()
+        host.append((a, b))
+        dev.append((ad, bd, torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")))
+    return dims, host, dev
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_grouped_matches_oracle_and_single_launch(table, dtype):
+    dims, host, dev = make_groups(96, seed=3, dtype=dtype, aligned_every=2, hi=300)
+    As, Bs, Cs = zip(*dev)
+    plan = pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs)
+    n_launch, tiles, chosen = plan.info()
+    say("%s plan: %d launches, %d tiles" % (dtype, n_launch, tiles))
+    plan.run()
+    torch.cuda.synchronize()
+    tol = 1e-5 if dtype == "f32" else 1e-2
+    for g, ((a, b), (ad, bd, cd)) in enumerate(zip(host, dev)):
+        ref = om.matmul(a, b, dtype)
+        got = cd.cpu()
+        assert not torch.isnan(got).any(), g
+        assert rel_fro(got.numpy(), ref) <= tol, (g, dims[g])
+        if g % 2 == 0:  # aligned: the single-product launch of the same program is bit-identical
+            C1 = torch.empty_like(cd)
+            pk.pk_matmul(table, chosen[g], dtype, ad, bd, C1)
+            torch.cuda.synchronize()
+            assert torch.equal(C1.cpu(), got), (g, dims[g], chosen[g])
+
+
+def test_grouped_graph_replays_match_eager(table):
+    dims, host, dev = make_groups(128, seed=5, dtype="f32", aligned_every=3)
+    As, Bs, Cs = zip(*dev)
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs)
+    plan.run()
+    torch.cuda.synchronize()
+    eager = [c.cpu().clone() for c in Cs]
+    plan.capture()
+    for rep in range(3):
+        for c in Cs:
+            c.zero_()                      # eager work between replays
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        for g, c in enumerate(Cs):
+            assert torch.equal(c.cpu(), eager[g]), (rep, g)
+
+
+def test_batched_one_shot_and_accumulate(table):
+    dims, host, dev = make_groups(40, seed=7, dtype="f32", aligned_every=1, hi=200)
+    As, Bs, Cs = zip(*dev)
+    pk.pk_matmul_batched(table, "f32", As, Bs, Cs)
+    first = [c.cpu().clone() for c in Cs]
+    for c in Cs:
+        c.zero_()
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, accumulate=True)
+    plan.run()
+    plan.run()
+    torch.cuda.synchronize()
+    for g, c in enumerate(Cs):
+        assert not torch.isnan(first[g]).any()
+        # small operands: every tile visited exactly once per run
+        assert torch.allclose(c.cpu(), 2 * first[g], rtol=1e-6, atol=1e-6), g
+
+
+def test_given_per_group_params(table):
+    dims, host, dev = make_groups(12, seed=9, dtype="f32", aligned_every=1, hi=260)
+    As, Bs, Cs = zip(*dev)
+    p = pk.params(family=pk.PK_FAMILY_MFMA, bm=64, bn=64, bk=32, wm=2, wn=2)
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, params=[p] * len(As))
+    n_launch, tiles, chosen = plan.info()
+    assert n_launch == 1
+    plan.run()
+    torch.cuda.synchronize()
+    for (a, b), (ad, bd, cd) in zip(host, dev):
+        assert rel_fro(cd.cpu().numpy(), om.matmul(a, b, "f32")) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_4096_products_sampled(table, dtype):
+    G = 4096
+    dims = inputs.group_dims(G, seed=0)
+    say("4096 products, %s: sum 2MNK = %.1f GFLOP" % (dtype, 2 * np.prod(dims, axis=1).sum() / 1e9))
+    # operands packed in three large buffers with 8-element-aligned rows
+    lda = (dims[:, 2] + 7) // 8 * 8
+    ldb = (dims[:, 1] + 7) // 8 * 8
+    offA = np.concatenate([[0], np.cumsum(dims[:, 0] * lda)])
+    offB = np.concatenate([[0], np.cumsum(dims[:, 2] * ldb)])
+    offC = np.concatenate([[0], np.cumsum(dims[:, 0] * dims[:, 1])])
+    Ah = inputs.uniform_f32((int(offA[-1]),), seed=11)
+    Bh = inputs.uniform_f32((int(offB[-1]),), seed=12)
+    if dtype == "bf16":
+        Ah, Bh = inputs.bf16_bits(Ah), inputs.bf16_bits(Bh)
+    Ad, Bd = Ah.cuda(), Bh.cuda()
+    Cd = torch.full((int(offC[-1]),), float("nan"), dtype=torch.float32, device="cuda")
+    As, Bs, Cs = [], [], []
+    for g, (M, N, K) in enumerate(dims):
+        M, N, K = int(M), int(N), int(K)
+        As.append(Ad[offA[g]:offA[g + 1]].view(M, int(lda[g]))[:, :K])
+        Bs.append(Bd[offB[g]:offB[g + 1]].view(K, int(ldb[g]))[:, :N])
+        Cs.append(Cd[offC[g]:offC[g + 1]].view(M, N))
+    plan = pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs)
+    plan.capture()
+    plan.replay()
+    torch.cuda.synchronize()
+    assert not torch.isnan(Cd).any()
+    rng = np.random.default_rng(1)
+    tol = 1e-5 if dtype == "f32" else 1e-2
+    for g in rng.choice(G, 24, replace=False):
+        M, N, K = (int(x) for x in dims[g])
+        a = Ah[offA[g]:offA[g + 1]].view(M, int(lda[g]))[:, :K].contiguous()
+        b = Bh[offB[g]:offB[g + 1]].view(K, int(ldb[g]))[:, :N].contiguous()
+        assert rel_fro(Cs[g].cpu().numpy(), om.matmul(a, b, dtype)) <= tol, g
