@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "matmul GFLOP/s and % FP32 peak: learned/case-table pick vs exhaustive best"
 FP32_PEAK_TFLOPS = 157.3
 TUNED = os.path.join(ROOT, "paper_1801_04348_amd", "data", "tuned_f32_gfx950.json")
+MODEL = os.path.join(ROOT, "paper_1801_04348_amd", "data", "costmodel_f32_gfx950.txt")
 PROFILES = os.path.join(ROOT, "profiles")
 COPY_BYTES = 256 << 20
 
@@ -65,12 +66,88 @@ def cpu_baseline(budget_s: float = 20.0):
                       % (len(done), flops / 1e9, secs)}
 
 
+def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
+    """4096 independent products, M, N, K each round(exp(U(ln 16, ln 512)))
+    from seed 0, operands packed in three buffers with rows padded to 8
+    elements: one grouped plan replayed from its captured graph, against a
+    loop of 4096 single-product launches (eager, and captured in a graph)."""
+    import numpy as np
+    G = 4096
+    dims = inputs.group_dims(G, seed=0)
+    lda = (dims[:, 2] + 7) // 8 * 8
+    ldb = (dims[:, 1] + 7) // 8 * 8
+    offA = np.concatenate([[0], np.cumsum(dims[:, 0] * lda)])
+    offB = np.concatenate([[0], np.cumsum(dims[:, 2] * ldb)])
+    offC = np.concatenate([[0], np.cumsum(dims[:, 0] * dims[:, 1])])
+    Ah = inputs.uniform_f32((int(offA[-1]),), seed=11)
+    Bh = inputs.uniform_f32((int(offB[-1]),), seed=12)
+    if dtype == "bf16":
+        Ah, Bh = inputs.bf16_bits(Ah), inputs.bf16_bits(Bh)
+    Ad, Bd = Ah.cuda(), Bh.cuda()
+    Cd = torch.empty((int(offC[-1]),), dtype=torch.float32, device="cuda")
+    As, Bs, Cs = [], [], []
+    for g, (M, N, K) in enumerate(dims):
+        M, N, K = int(M), int(N), int(K)
+        As.append(Ad[offA[g]:offA[g + 1]].view(M, int(lda[g]))[:, :K])
+        Bs.append(Bd[offB[g]:offB[g + 1]].view(K, int(ldb[g]))[:, :N])
+        Cs.append(Cd[offC[g]:offC[g + 1]].view(M, N))
+    flops = float(2 * np.prod(dims.astype(np.float64), axis=1).sum())
+    es = 2 if dtype == "bf16" else 4
+    peak = 2.5e15 if dtype == "bf16" else 157.3e12
+    per_bytes = es * (dims[:, 0] * dims[:, 2] + dims[:, 2] * dims[:, 1]) + 4.0 * dims[:, 0] * dims[:, 1]
+    roof = float(np.sum(np.maximum(2.0 * np.prod(dims.astype(np.float64), axis=1) / peak, per_bytes / 8e12)))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    plan = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=policy)
+    n_launch, tiles, _ = plan.info()
+    plan.capture()
+    t_graph = timed(lambda: plan.replay())
+    t_plan = timed(lambda: plan.run())
+    picks = [pk.pk_select(tbl, dtype, int(M), int(N), int(K), pk.PK_POLICY_CASE) for (M, N, K) in dims]
+
+    def loop():
+        for g in range(G):
+            pk.pk_matmul(tbl, picks[g], dtype, As[g], Bs[g], Cs[g])
+    t_loop = timed(loop)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        loop()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        loop()
+    t_loop_graph = timed(lambda: graph.replay())
+    return {"products": G, "gflop": round(flops / 1e9, 2), "launches": n_launch, "tiles": tiles,
+            "grouped_graph_gflops": round(flops / t_graph / 1e9, 1),
+            "grouped_gflops": round(flops / t_plan / 1e9, 1),
+            "loop_gflops": round(flops / t_loop / 1e9, 1),
+            "loop_graph_gflops": round(flops / t_loop_graph / 1e9, 1),
+            "speedup_vs_loop": round(t_loop / t_graph, 2),
+            "speedup_vs_loop_graph": round(t_loop_graph / t_graph, 2),
+            "pct_summed_roofline": round(roof / t_graph, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--policy", choices=["case", "learned"], default="case")
+    ap.add_argument("--policy", choices=["auto", "case", "learned"], default="auto",
+                    help="auto: the learned cost model when one for this machine is shipped, else the case table")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the 4096-product grouped comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
@@ -98,7 +175,18 @@ def main():
     if args.save_machine:
         with open(args.save_machine, "w") as f:
             json.dump(machine, f)
-    policy = pk.PK_POLICY_CASE if args.policy == "case" else pk.PK_POLICY_LEARNED
+    model_note = None
+    have_model = False
+    if args.policy in ("auto", "learned") and os.path.exists(MODEL):
+        try:
+            pk.pk_case_table_set_costmodel(tbl, pk.pk_costmodel_load(MODEL))
+            have_model = True
+        except pk.PkError as e:
+            model_note = str(e)
+    if args.policy == "learned" and not have_model:
+        sys.exit("no usable cost model: %s" % (model_note or MODEL))
+    policy_name = "learned" if have_model and args.policy != "case" else "case"
+    policy = pk.PK_POLICY_LEARNED if policy_name == "learned" else pk.PK_POLICY_CASE
     shapes = inputs.sweep_shapes()
     big = max(max(s) for s in shapes)
     Abuf = inputs.uniform_f32((big * big,), seed=0).cuda()
@@ -193,49 +281,66 @@ def main():
         ms = per_shape_ms[s]
         large["x".join(map(str, s))] = {"gflops": round(2.0 * s[0] * s[1] * s[2] / ms / 1e6, 1),
                                          "pct_fp32_peak": round(2.0 * s[0] * s[1] * s[2] / ms / 1e9 / FP32_PEAK_TFLOPS, 4)}
+    # per shape, interleaved: the exhaustively-best branch (tuning store of this
+    # machine), the CASE pick and the LEARNED pick (untimed for `value`)
     exhaustive = None
+    best = {}
     if os.path.exists(TUNED):
         with open(TUNED) as f:
             tuned = json.load(f)
-        best = {tuple(r["shape"]): r for r in tuned["shapes"]}
-        ratios, best_ms_total, pick_ms_total = [], 0.0, 0.0
+        if tuned["machine"]["regs_block"] == machine["regs_block"]:
+            best = {tuple(r["shape"]): pk.params(**r["params"]) for r in tuned["shapes"]}
+    if best:
+        def t_of(p, o, reps=3):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            pk.pk_matmul(tbl, p, "f32", o["A"], o["B"], o["C"])
+            e[0].record()
+            for _ in range(reps):
+                pk.pk_matmul(tbl, p, "f32", o["A"], o["B"], o["C"])
+            e[1].record()
+            torch.cuda.synchronize()
+            return e[0].elapsed_time(e[1]) / reps
+        tot = {"best": 0.0, "case": 0.0, "learned": 0.0}
+        ratios = {"case": [], "learned": []}
+        fl = 0.0
         for o in ops:
             key = (o["M"], o["N"], o["K"])
             if key not in best:
                 continue
-            bp = pk.params(**best[key]["params"])
-            reps = 3
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            pk.pk_matmul(tbl, bp, "f32", o["A"], o["B"], o["C"])
-            e[0].record()
-            for _ in range(reps):
-                pk.pk_matmul(tbl, bp, "f32", o["A"], o["B"], o["C"])
-            e[1].record()
-            for _ in range(reps):
-                pk.pk_matmul(tbl, o["p"], "f32", o["A"], o["B"], o["C"])
-            e[2].record()
-            torch.cuda.synchronize()
-            tb = e[0].elapsed_time(e[1]) / reps
-            tp = e[1].elapsed_time(e[2]) / reps
-            best_ms_total += tb
-            pick_ms_total += tp
-            ratios.append(min(tb / tp, 1.0) if tp > 0 else 1.0)
-        if ratios:
-            exhaustive = {"shapes": len(ratios),
-                          "best_gflops": round(sum(o["flops"] for o in ops) / best_ms_total / 1e6, 1),
-                          "pick_gflops": round(sum(o["flops"] for o in ops) / pick_ms_total / 1e6, 1),
-                          "pick_over_best_geomean": round(math.exp(sum(map(math.log, ratios)) / len(ratios)), 4),
-                          "pick_over_best_min": round(min(ratios), 4)}
+            fl += o["flops"]
+            tb = t_of(best[key], o)
+            tc = t_of(pk.pk_select(tbl, "f32", *key, pk.PK_POLICY_CASE), o)
+            tot["best"] += tb
+            tot["case"] += tc
+            ratios["case"].append(min(tb / tc, 1.0))
+            if have_model:
+                tl = t_of(pk.pk_select(tbl, "f32", *key, pk.PK_POLICY_LEARNED), o)
+                tot["learned"] += tl
+                ratios["learned"].append(min(tb / tl, 1.0))
+        geo = lambda r: round(math.exp(sum(map(math.log, r)) / len(r)), 4)
+        exhaustive = {"shapes": len(ratios["case"]), "best_gflops": round(fl / tot["best"] / 1e6, 1),
+                      "case_gflops": round(fl / tot["case"] / 1e6, 1),
+                      "case_over_best_geomean": geo(ratios["case"]), "case_over_best_min": round(min(ratios["case"]), 4)}
+        if have_model:
+            sel, fb = pk.pk_case_table_learned_stats(tbl)
+            exhaustive.update({"learned_gflops": round(fl / tot["learned"] / 1e6, 1),
+                               "learned_over_best_geomean": geo(ratios["learned"]),
+                               "learned_over_best_min": round(min(ratios["learned"]), 4),
+                               "learned_fallback_rate": round(fb / max(sel, 1), 3)})
+
+    grouped = None
+    if not args.no_grouped:
+        grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "fp32 matmul sweep, M,N,K in {512,1000,2048,3000,4096,8192} (216 shapes), "
-                                  "uniform[-1,1) operands, %s pick per shape" % args.policy,
-                      "shapes": len(shapes), "gflop_per_step": round(flops_step / 1e9, 1), "policy": args.policy,
+                                  "uniform[-1,1) operands, %s pick per shape" % policy_name,
+                      "shapes": len(shapes), "gflop_per_step": round(flops_step / 1e9, 1), "policy": policy_name,
                       "parallelism": "none (1 GPU)"},
            "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
-           "large_shapes": large, "exhaustive": exhaustive, "roofline": roofline,
+           "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "roofline": roofline,
            "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -78,13 +78,16 @@ typedef struct {
  * is run on. */
 #define PK_FAMILY_VALU 0  /* the blocked kernel of Section 2 (Fig. 3, Fig. 4), f32 and i32 */
 #define PK_FAMILY_MFMA 1  /* LDS-tiled matrix-core kernel, f32 and bf16 */
-#define PK_NUM_FAMILIES 2
+#define PK_FAMILY_TRANSPOSE 2 /* matrix transposition (Section 5.2, Fig. 7), 4-byte elements */
+#define PK_NUM_FAMILIES 3
 
 /* Strategy bits of the VALU family (a variant is the set of strategies applied):
  * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
  * PK_VALU_NOLDS - operands read straight from global memory, no LDS (decision (4b)) */
 #define PK_VALU_GRAN 1
 #define PK_VALU_NOLDS 2
+/* Strategy bits of the transposition family: PK_VALU_GRAN (one element per
+ * work-item) and PK_VALU_NOLDS (no LDS tile), as for the VALU family. */
 /* Strategy bits of the MFMA family:
  * PK_MFMA_SINGLE - one LDS stage instead of two (halves the LDS tile footprint)
  * PK_MFMA_GROUPED marks the persistent grouped instances of the same programs
@@ -100,7 +103,10 @@ typedef struct {
  *   (the paper's B0), s = outputs per thread along N (the paper's s), bk =
  *   K extent of an LDS tile (the paper fixes it to B0; 0 means "= by").
  * MFMA family: bm x bn output tile per workgroup, bk its K extent, wm x wn
- *   wavefronts of 64 lanes; unused fields are 0. */
+ *   wavefronts of 64 lanes; unused fields are 0.
+ * Transposition family: bx = work-items along the columns of A (the paper's
+ *   B1), by = work-items along its rows (B0), s = elements per work-item (s);
+ *   a workgroup moves a (by * s) x bx tile of A. */
 typedef struct {
     int32_t family;
     int32_t leaf;
@@ -243,6 +249,22 @@ int pk_matmul_batched(const pk_table *tbl, pk_dtype dtype, int32_t G, const int6
                       const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
                       const int64_t *ldb, void *const *C, const int64_t *ldc, const pk_params *per_group_or_null,
                       void *hip_stream);
+
+/* ------------------------------------------------------------------ transposition */
+/* C (N x M) = A (M x N) transposed, 4-byte elements copied bit for bit
+ * (dtype PK_F32 or PK_I32), row-major with leading dimensions lda >= N,
+ * ldc >= M; asynchronous on hip_stream.  params_or_null: family
+ * PK_FAMILY_TRANSPOSE, resolved as in pk_matmul (NULL: the CASE choice).
+ * Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
+ * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NOT_INSTANTIATED, PK_ERR_HIP. */
+int pk_transpose(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, const void *A, int64_t lda,
+                 void *C, int64_t ldc, int64_t M, int64_t N, void *hip_stream);
+
+/* Choice of a transposition leaf and parameters for an M x N matrix:
+ * PK_POLICY_CASE (analytic: bytes over bandwidth by program, with wave
+ * quantisation) or PK_POLICY_EXHAUSTIVE (every feasible candidate timed on
+ * scratch buffers; synchronizes; cached).  Errors as pk_select. */
+int pk_select_transpose(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int policy, pk_params *out);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */

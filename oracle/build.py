@@ -1,4 +1,5 @@
-"""Compiles ``oracle/matmul.c`` into ``oracle/_build/liboracle.so`` with gcc.
+"""Compiles ``oracle/matmul.c`` and ``oracle/transpose.c`` into
+``oracle/_build/liboracle.so`` with gcc.
 
 Test infrastructure only.  Flags keep IEEE semantics (no fast-math, no FMA
 contraction) so the double sums are taken exactly in the written order.
@@ -10,18 +11,18 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "matmul.c")
+SOURCES = [os.path.join(HERE, "matmul.c"), os.path.join(HERE, "transpose.c")]
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liboracle.so")
 
 
 def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(s) for s in SOURCES):
         return LIB
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
-           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, SRC]
+           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp] + SOURCES
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -15,6 +15,11 @@ enumeration over a grid of machines and the whole program-parameter domain:
   stages) and {single} (one).  One stage holds, in float32, an A tile bm x
   (bk + 4) and a B tile bk x (bn + 4); in bfloat16 an A tile bm x (bk + 8) and
   a transposed B tile bn x (bk + 8); threads: 64 * wm * wn.
+* Transposition family (Section 5.2, Fig. 7): program parameters bx (the
+  paper's B1), by (B0), s; programs as in the VALU family; the cached program
+  holds one (by * s') x bx tile padded by one element per row: 4 * (by * s')
+  * (bx + 1) bytes; threads bx * by.  One compiled program serves every
+  4-byte element type.
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -36,7 +41,7 @@ import numpy as np
 from . import comprehensive as co
 
 F32, I32, BF16 = 0, 1, 2
-VALU, MFMA = 0, 1
+VALU, MFMA, TRANSPOSE = 0, 1, 2
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 
@@ -63,6 +68,13 @@ def valu_lds(variant: int, bx: int, by: int, s: int) -> int:
     return 4 * (by * (bk + 1) + bk * bx * outs)
 
 
+def transpose_lds(variant: int, bx: int, by: int, s: int) -> int:
+    if variant & NOLDS:
+        return 0
+    outs = 1 if variant & GRAN else s
+    return 4 * by * outs * (bx + 1)
+
+
 def mfma_lds(dtype: int, variant: int, bm: int, bn: int, bk: int) -> int:
     stages = 1 if variant & SINGLE else 2
     if dtype == F32:
@@ -78,18 +90,19 @@ class InstanceData:
     def __init__(self, instances: List[dict]):
         self.by_key = {}
         for e in instances:
-            if e["family"] == VALU:
-                key = (VALU, e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
+            if e["family"] in (VALU, TRANSPOSE):
+                key = (e["family"], e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
             else:
                 key = (MFMA, e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"], e["wm"], e["wn"])
             self.by_key[key] = e
 
     def regs(self, family: int, dtype: int, variant: int, point: Tuple[int, ...]):
-        if family == VALU:
+        if family in (VALU, TRANSPOSE):
             bx, by, s = point
             kernel = variant & NOLDS
             outs = 1 if variant & GRAN else s
-            e = self.by_key.get((VALU, dtype, kernel, bx, by, outs))
+            dt = F32 if family == TRANSPOSE else dtype
+            e = self.by_key.get((family, dt, kernel, bx, by, outs))
         else:
             e = self.by_key.get((MFMA, dtype, variant & SINGLE) + tuple(point))
         if e is None or "vgpr" not in e:
@@ -98,7 +111,7 @@ class InstanceData:
 
 
 def threads(family: int, point) -> int:
-    if family == VALU:
+    if family in (VALU, TRANSPOSE):
         return point[0] * point[1]
     return 64 * point[3] * point[4]
 
@@ -106,6 +119,8 @@ def threads(family: int, point) -> int:
 def lds(family: int, dtype: int, variant: int, point) -> int:
     if family == VALU:
         return valu_lds(variant, *point)
+    if family == TRANSPOSE:
+        return transpose_lds(variant, *point)
     return mfma_lds(dtype, variant, point[0], point[1], point[2])
 
 
@@ -117,7 +132,7 @@ def fits(inst: InstanceData, family, dtype, variant, point, Z, V, T) -> bool:
 
 
 def variants(family: int):
-    return VALU_VARIANTS if family == VALU else MFMA_VARIANTS
+    return MFMA_VARIANTS if family == MFMA else VALU_VARIANTS
 
 
 def machine_grid():
@@ -136,7 +151,26 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
     its predecessor), 0, and one value above all of them, so the finite
     enumeration decides the same as integers without bound."""
     pts = [tuple(p) for p in points]
-    if family == VALU:
+    if family == TRANSPOSE:
+        program = ["bx", "by", "s"]
+        strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
+                      co.Strategy("nolds", False, frozenset({"r_Z", "r_V"}))]
+        names = {0: "rho_tiled", GRAN: "rho_tiled_s1", NOLDS: "rho_direct", GRAN | NOLDS: "rho_direct_s1"}
+
+        def lds_poly(applied):
+            a = set(applied)
+            if "nolds" in a:
+                return co.Poly.const(0)
+            if "gran" in a:
+                return co.parse_poly("4*by*(bx+1)")
+            return co.parse_poly("4*by*s*(bx+1)")
+
+        def bits(applied):
+            a = set(applied)
+            return (GRAN if "gran" in a else 0) | (NOLDS if "nolds" in a else 0)
+
+        thr = co.parse_poly("bx*by")
+    elif family == VALU:
         program = ["bx", "by", "s"]
         strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
                       co.Strategy("nolds", False, frozenset({"r_Z", "r_V"}))]

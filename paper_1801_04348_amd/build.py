@@ -37,13 +37,13 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC,
           "-Wno-unused-command-line-argument"]
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
-HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp"]
+HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp"]
 DEVICE_SOURCES = ["costmodel.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}
 DT_CTYPE = {F32: "float", I32: "int32_t"}
-FAM_VALU, FAM_MFMA = 0, 1
+FAM_VALU, FAM_MFMA, FAM_TR = 0, 1, 2
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
@@ -51,6 +51,9 @@ MFMA_GROUPED = 2
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
 VALU_S = (1, 2, 4, 8)
+TR_BX = (16, 32, 64)
+TR_BY = (4, 8, 16, 32)
+TR_S = (1, 2, 4, 8)
 MFMA_F32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (128, 128, 32, 2, 2),
             (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4)]
 MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128, 128, 64, 2, 2),
@@ -94,6 +97,21 @@ def instances():
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
+    # transposition: tiled and direct programs (bit copies of 4-byte elements)
+    for bx in TR_BX:
+        for by in TR_BY:
+            if bx * by > 1024:
+                continue
+            for s in TR_S:
+                for nolds in (0, 1):
+                    kind = "direct" if nolds else "tiled"
+                    name = "pk_transpose_%s_bx%d_by%d_s%d" % (kind, bx, by, s)
+                    body = "pkk::transpose_%s<%d, %d, %d>(a);" % (kind, by, bx, s)
+                    entry = dict(family=FAM_TR, variant=VALU_NOLDS if nolds else 0, dtype=F32, bx=bx, by=by, s=s,
+                                 bk=0, bm=0, bn=0, wm=0, wn=0, threads=bx * by,
+                                 lds=0 if nolds else 4 * by * s * (bx + 1), tile_m=by * s, tile_n=bx,
+                                 args="pkk::TrArgs a")
+                    out.append(("transpose_bx%d" % bx, name, body, entry))
     # persistent grouped instances of the MFMA programs up to 128 x 128
     gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
     for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):
@@ -105,7 +123,7 @@ def instances():
                 body = "pkk::%s<%d, %d, %d, %d, %d, %d>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages)
                 entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE),
                              dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
-                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, grouped=True)
+                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, args="pkk::GroupArgs g")
                 out.append(("grouped_%s" % DT_NAME[dt], name, body, entry))
     return out
 
@@ -124,9 +142,10 @@ def generate():
     tus = []
     for grp, items in sorted(groups.items()):
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
-                 "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"', ""]
+                 "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"',
+                 '#include "kernels/transpose.hpp"', ""]
         for name, body, entry in items:
-            arg = "pkk::GroupArgs g" if entry.get("grouped") else "pkk::MmArgs a"
+            arg = entry.get("args", "pkk::MmArgs a")
             lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'
                          % (entry["threads"], name, arg, body))
         lines.append("")

@@ -205,8 +205,8 @@ int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table
                 pk_table::Part part;
                 part.family = family;
                 part.dtype = dtype;
-                const bool ok = family == PK_FAMILY_VALU ? (dtype == PK_F32 || dtype == PK_I32)
-                                                         : (dtype == PK_F32 || dtype == PK_BF16);
+                const bool ok = family == PK_FAMILY_MFMA ? (dtype == PK_F32 || dtype == PK_BF16)
+                                                         : (dtype == PK_F32 || dtype == PK_I32);
                 part.supported = ok;
                 if (ok) {
                     part.fam = matmul_family(family, dtype);
@@ -386,6 +386,8 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
             if (rc != PK_OK) return rc;
             params_or_null = &sel;
         }
+        if (params_or_null->family == PK_FAMILY_TRANSPOSE)
+            return fail(PK_ERR_INVALID_ARG, "transposition parameters given to a product");
         pk_params q;
         const KernelEntry *e = nullptr;
         int rc = resolve(tbl, params_or_null, (int)dtype, &q, &e);

@@ -23,6 +23,12 @@
 // The register-pressure strategy (1) of the experiments has no counterpart:
 // the compiler already fits each instance's registers to its launch bounds.
 //
+// Transposition family (Section 5.2, Fig. 7): program parameters bx (the
+// paper's B1, work-items along the columns of A), by (B0), s (elements per
+// work-item); strategies gran and nolds as in the VALU family.  LDS bytes of
+// the cached program: 4 * (by * s) * (bx + 1) -- one padded tile (the paper's
+// program caches a and c separately, 2 s B0 B1 words).
+//
 // MFMA family, program parameters bm, bn (output tile), bk (K tile), wm, wn
 // (wavefront grid).  Strategy:
 //   single (source; sigma = {r_Z, r_V}) one LDS stage instead of two (also no
@@ -43,6 +49,10 @@ struct MfmaPoint {
 // Program-parameter domains.  VALU: {4, 8, 16, 32}^2 x {1, 2, 4, 8}.
 const int kValuB[] = {4, 8, 16, 32};
 const int kValuS[] = {1, 2, 4, 8};
+
+const int kTrBx[] = {16, 32, 64};
+const int kTrBy[] = {4, 8, 16, 32};
+const int kTrS[] = {1, 2, 4, 8};
 
 const MfmaPoint kMfmaF32[] = {
     {64, 64, 32, 2, 2},   {128, 64, 32, 2, 2},  {64, 128, 32, 2, 2},  {128, 128, 32, 2, 2},
@@ -137,6 +147,41 @@ Family matmul_family(int family, int dtype) {
         };
         return f;
     }
+    if (family == PK_FAMILY_TRANSPOSE) {
+        if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("transposition: 4-byte elements only");
+        const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
+                  s = add_sym(f, "s", SYM_PROGRAM);
+        const int rho_t = add_sym(f, "rho_tiled", SYM_TABLE), rho_t1 = add_sym(f, "rho_tiled_s1", SYM_TABLE),
+                  rho_d = add_sym(f, "rho_direct", SYM_TABLE), rho_d1 = add_sym(f, "rho_direct_s1", SYM_TABLE);
+        f.point_syms = {bx, by, s};
+        for (int x : kTrBx)
+            for (int y : kTrBy)
+                for (int z : kTrS) f.points.push_back({x, y, z});
+        const Poly lds_full = P(4) * S(by) * S(s) * (S(bx) + P(1));
+        const Poly lds_g1 = P(4) * S(by) * (S(bx) + P(1));
+        CounterDef rz{"r_Z", false, m.Z, nullptr};
+        rz.value = [=](uint32_t ap) {
+            if (ap & PK_VALU_NOLDS) return P(0);
+            if (ap & PK_VALU_GRAN) return lds_g1;
+            return lds_full;
+        };
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) {
+            const bool g = ap & PK_VALU_GRAN, d = ap & PK_VALU_NOLDS;
+            return S(d ? (g ? rho_d1 : rho_d) : (g ? rho_t1 : rho_t));
+        };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return S(bx) * S(by); };
+        f.counters = {rz, rv, rt};
+        f.strategies = {StrategyDef{"gran", false, 0b011u}, StrategyDef{"nolds", false, 0b011u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            int variant = 0;
+            if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
+            if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
+            return table_regs(PK_FAMILY_TRANSPOSE, variant, PK_F32, pt, 64);
+        };
+        return f;
+    }
     if (family == PK_FAMILY_MFMA) {
         if (dtype != PK_F32 && dtype != PK_BF16) throw std::runtime_error("MFMA family: f32 and bf16 only");
         const int bm = add_sym(f, "bm", SYM_PROGRAM), bn = add_sym(f, "bn", SYM_PROGRAM),
@@ -169,6 +214,10 @@ Family matmul_family(int family, int dtype) {
 }
 
 bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
+    if (family == PK_FAMILY_TRANSPOSE) {
+        *pt = {p.bx, p.by, p.s};
+        return true;
+    }
     if (family == PK_FAMILY_VALU) {
         if (p.bk != 0 && p.bk != p.by) return false;  // the paper's K tile: bk = by
         *pt = {p.bx, p.by, p.s};
@@ -184,11 +233,11 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
     p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
-    if (family == PK_FAMILY_VALU) {
+    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
         p->bx = (int32_t)pt[0];
         p->by = (int32_t)pt[1];
         p->s = (int32_t)pt[2];
-        p->bk = (int32_t)pt[1];
+        p->bk = family == PK_FAMILY_VALU ? (int32_t)pt[1] : 0;
     } else {
         p->bm = (int32_t)pt[0];
         p->bn = (int32_t)pt[1];
@@ -221,7 +270,8 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     // instance; no-LDS runs the direct kernel; MFMA single runs one stage
     int kind = 0;
     std::vector<int64_t> q = pt;
-    if (family == PK_FAMILY_VALU) {
+    if (family == PK_FAMILY_TRANSPOSE) dtype = PK_F32;  // a bit copy: one instance serves every 4-byte type
+    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
         if (variant & PK_VALU_GRAN) q[2] = 1;
         kind = variant & PK_VALU_NOLDS;
     } else {
@@ -229,7 +279,7 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     }
     for (const auto &e : registry()) {
         if (e.family != family || e.dtype != dtype || e.variant != kind) continue;
-        if (family == PK_FAMILY_VALU) {
+        if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
             if (e.bx == q[0] && e.by == q[1] && e.s == q[2]) return &e;
         } else {
             if (e.bm == q[0] && e.bn == q[1] && e.bk == q[2] && e.wm == q[3] && e.wn == q[4]) return &e;

@@ -92,7 +92,7 @@ void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *
 std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, const void *A,
                                 int64_t lda, const void *B, int64_t ldb) {
     std::vector<Candidate> out;
-    for (int family = 0; family < PK_NUM_FAMILIES; ++family) {
+    for (int family : {PK_FAMILY_VALU, PK_FAMILY_MFMA}) {  // the product families
         const pk_table::Part *part = tbl->part(family, dtype);
         if (!part || !part->supported) continue;
         if (A && !data_ok(family, dtype, A, lda, B, ldb)) continue;

@@ -34,7 +34,7 @@ PK_ERR_BUFFER_TOO_SMALL = -7
 PK_ERR_PARSE = -8
 
 PK_F32, PK_I32, PK_BF16 = 0, 1, 2
-PK_FAMILY_VALU, PK_FAMILY_MFMA = 0, 1
+PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE = 0, 1, 2
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
@@ -121,6 +121,10 @@ def lib():
                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
         L.pk_measure.argtypes = [vp, i32, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.POINTER(pk_params),
                                  ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(ctypes.c_int)]
+        L.pk_transpose.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, i64, i64, vp]
+        L.pk_transpose.restype = i32
+        L.pk_select_transpose.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_transpose.restype = i32
         L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
         L.pk_kernel_name.restype = ctypes.c_char_p
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -260,6 +264,23 @@ def pk_measure(tbl: Table, dtype, M: int, N: int, K: int, A=None, B=None, C=None
     _check(lib().pk_measure(tbl.handle, _dt(dtype), a, lda, b, ldb, c, ldc, M, N, K, ps, secs, cap,
                             ctypes.byref(n)))
     return [(ps[i], secs[i]) for i in range(n.value)]
+
+
+def pk_select_transpose(tbl: Table, dtype, M: int, N: int, policy: int = PK_POLICY_CASE) -> pk_params:
+    out = pk_params()
+    _check(lib().pk_select_transpose(tbl.handle, _dt(dtype), M, N, policy, ctypes.byref(out)))
+    return out
+
+
+def pk_transpose(tbl: Table, p, dtype, A, C, stream=None):
+    """C = A^T on the device (4-byte elements); A: (M, N), C: (N, M)."""
+    M, N = A.shape
+    if tuple(C.shape) != (N, M):
+        raise ValueError("C must be (N, M)")
+    a, lda = _ptr_ld(A)
+    c, ldc = _ptr_ld(C)
+    _check(lib().pk_transpose(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
+                              c, max(ldc, M), M, N, _stream(stream)))
 
 
 def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:

@@ -121,6 +121,8 @@ def test_lds_counter_equals_compiled_lds(gfx_desc):
         assert e["lds_bytes"] == e["lds_compiled"], e["name"]
         if e["family"] == en.VALU:
             assert e["lds_bytes"] == en.valu_lds(e["variant"], e["bx"], e["by"], e["s"])
+        elif e["family"] == en.TRANSPOSE:
+            assert e["lds_bytes"] == en.transpose_lds(e["variant"], e["bx"], e["by"], e["s"])
         else:
             assert e["lds_bytes"] == en.mfma_lds(e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"])
         assert e["scratch"] == 0, e["name"]   # no register spills in any instance
@@ -192,7 +194,8 @@ def test_optimality_definition_3_iv(gfx_desc):
     # for each counter, some leaf at which no strategy of sigma(counter) is
     # left unapplied (so none can lower it further)
     sigma = {0: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
-             1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()}}
+             1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()},
+             2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
     for part in gfx_desc["parts"]:
         for counter, strategies in sigma[part["family"]].items():
             assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
@@ -226,6 +229,25 @@ def test_select_returns_feasible_choice(gfx_table):
             p = pk.pk_select(gfx_table, dt, *shp)
             leaf, var = pk.pk_case_table_lookup(gfx_table, dt, p)
             assert leaf == p.leaf and var == p.variant
+
+
+def test_transpose_table_refuses_oversized_workgroups(gfx_table):
+    # bx * by = 64 * 32 = 2048 work-items exceeds T = 1024: the refuse branch
+    # of r_T has no strategy, so no leaf holds there
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_case_table_lookup(gfx_table, "f32", pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=64, by=32, s=1))
+    assert e.value.code == pk.PK_ERR_NO_FEASIBLE_BRANCH
+    leaf, var = pk.pk_case_table_lookup(gfx_table, "f32", pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=32, by=8, s=2))
+    assert var == 0
+    p = pk.pk_select_transpose(gfx_table, "f32", 16384, 16384)
+    assert p.family == pk.PK_FAMILY_TRANSPOSE
+    # a machine with 4 KiB of LDS: the cached tile of (8 * 8) x 33 words no
+    # longer fits, granularity is reduced first, then LDS is dropped
+    small = pk.pk_case_table_build(0, machines.variant(lds_block=4096, lds_cu=65536))
+    leaf, var = pk.pk_case_table_lookup(small, "f32", pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=32, by=8, s=8))
+    assert var == pk.PK_VALU_GRAN
+    leaf, var = pk.pk_case_table_lookup(small, "f32", pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=64, by=16, s=8))
+    assert var == pk.PK_VALU_GRAN | pk.PK_VALU_NOLDS
 
 
 def test_select_no_feasible_branch():
