@@ -140,6 +140,53 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
             "pct_summed_roofline": round(roof / t_graph, 4)}
 
 
+def madd_section(tbl, pk, torch, inputs, n=16384, reps=10):
+    """Matrix addition (Section 1, Fig. 1) of two order-2^14 float32 matrices:
+    the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
+    traffic (two reads and one write per element) against 8 TB/s."""
+    A = inputs.uniform_f32((n, n), seed=0).cuda()
+    B = inputs.uniform_f32((n, n), seed=1).cuda()
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    out = {"order": n, "bytes": 12 * n * n}
+    for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+        p = pk.pk_select_madd(tbl, "f32", n, n, pol)
+        pk.pk_madd(tbl, p, "f32", A, B, C)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pk.pk_madd(tbl, p, "f32", A, B, C)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / reps * 1e-3
+        out[name] = {"kernel": pk.pk_kernel_name(tbl, p, "f32"), "gbps": round(12 * n * n / s / 1e9, 1),
+                     "frac_hbm": round(12 * n * n / s / 8e12, 4)}
+    return out
+
+
+def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
+    """Transposition of an order-2^14 float32 matrix (the paper's Table 3
+    size): the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
+    traffic (one read and one write per element) against 8 TB/s."""
+    A = inputs.uniform_f32((n, n), seed=0).cuda()
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    out = {"order": n, "bytes": 8 * n * n}
+    for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+        p = pk.pk_select_transpose(tbl, "f32", n, n, pol)
+        pk.pk_transpose(tbl, p, "f32", A, C)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pk.pk_transpose(tbl, p, "f32", A, C)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / reps * 1e-3
+        out[name] = {"kernel": pk.pk_kernel_name(tbl, p, "f32"), "gbps": round(8 * n * n / s / 1e9, 1),
+                     "frac_hbm": round(8 * n * n / s / 8e12, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--policy", choices=["auto", "case", "learned"], default="auto",
                     help="auto: the learned cost model when one for this machine is shipped, else the case table")
-    ap.add_argument("--no-grouped", action="store_true", help="skip the 4096-product grouped comparison")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
@@ -328,6 +375,8 @@ def main():
                                "learned_over_best_min": round(min(ratios["learned"]), 4),
                                "learned_fallback_rate": round(fb / max(sel, 1), 3)})
 
+    transpose = None if args.no_grouped else transpose_section(tbl, pk, torch, inputs)
+    madd = None if args.no_grouped else madd_section(tbl, pk, torch, inputs)
     grouped = None
     if not args.no_grouped:
         grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
@@ -340,7 +389,9 @@ def main():
                       "shapes": len(shapes), "gflop_per_step": round(flops_step / 1e9, 1), "policy": policy_name,
                       "parallelism": "none (1 GPU)"},
            "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
-           "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "roofline": roofline,
+           "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "transpose": transpose,
+           "madd": madd,
+           "roofline": roofline,
            "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

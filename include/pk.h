@@ -11,7 +11,8 @@
  *
  * This library holds
  *   - the symbolic engine of Algorithms 1 and 2 (pk_co_solve),
- *   - the case tables of its matmul kernel families, built once per process
+ *   - the case tables of its kernel families (matmul, and the transposition
+ *     and matrix addition of the paper's examples), built once per process
  *     and bound to the machine parameters read from hipDeviceProp_t
  *     (pk_case_table_build),
  *   - load-time selection of a leaf and its program parameters (pk_select),
@@ -25,7 +26,9 @@
  *   - device pointers are HIP device addresses owned by the caller, which must
  *     keep them alive until the work queued on the given stream completes;
  *   - hip_stream is a hipStream_t (NULL = the default stream); matmul calls
- *     are asynchronous on it.
+ *     are asynchronous on it;
+ *   - every dimension (M, N, K) is at most 2^31 - 2^16 (PK_ERR_INVALID_ARG
+ *     beyond): kernels index rows and columns in 32-bit integers.
  */
 #ifndef PK_H
 #define PK_H
@@ -79,7 +82,8 @@ typedef struct {
 #define PK_FAMILY_VALU 0  /* the blocked kernel of Section 2 (Fig. 3, Fig. 4), f32 and i32 */
 #define PK_FAMILY_MFMA 1  /* LDS-tiled matrix-core kernel, f32 and bf16 */
 #define PK_FAMILY_TRANSPOSE 2 /* matrix transposition (Section 5.2, Fig. 7), 4-byte elements */
-#define PK_NUM_FAMILIES 3
+#define PK_FAMILY_MADD 3      /* matrix addition (Section 1, Fig. 1 and Fig. 2), f32 and i32 */
+#define PK_NUM_FAMILIES 4
 
 /* Strategy bits of the VALU family (a variant is the set of strategies applied):
  * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
@@ -106,7 +110,10 @@ typedef struct {
  *   wavefronts of 64 lanes; unused fields are 0.
  * Transposition family: bx = work-items along the columns of A (the paper's
  *   B1), by = work-items along its rows (B0), s = elements per work-item (s);
- *   a workgroup moves a (by * s) x bx tile of A. */
+ *   a workgroup moves a (by * s) x bx tile of A.
+ * Matrix-addition family: bx = work-items along a row (Fig. 2's B1), by =
+ *   rows per workgroup (B0), s = elements per work-item (2 in Fig. 2's K1);
+ *   strategy bit PK_VALU_GRAN (one element per work-item, Fig. 2's K2). */
 typedef struct {
     int32_t family;
     int32_t leaf;
@@ -265,6 +272,16 @@ int pk_transpose(const pk_table *tbl, const pk_params *params_or_null, pk_dtype 
  * quantisation) or PK_POLICY_EXHAUSTIVE (every feasible candidate timed on
  * scratch buffers; synchronizes; cached).  Errors as pk_select. */
 int pk_select_transpose(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int policy, pk_params *out);
+
+/* ------------------------------------------------------------------ matrix addition */
+/* C = A + B (M x N, row-major, leading dimensions >= N), f32 (one rounding)
+ * or i32 (modulo 2^32); asynchronous on hip_stream.  params_or_null: family
+ * PK_FAMILY_MADD, resolved as in pk_matmul (NULL: the CASE choice).  The
+ * family's counters are registers per workgroup and work-items per workgroup,
+ * the two machine parameters of Fig. 2.  Errors as pk_transpose. */
+int pk_madd(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, const void *A, int64_t lda,
+            const void *B, int64_t ldb, void *C, int64_t ldc, int64_t M, int64_t N, void *hip_stream);
+int pk_select_madd(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int policy, pk_params *out);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */

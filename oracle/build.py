@@ -1,4 +1,4 @@
-"""Compiles ``oracle/matmul.c`` and ``oracle/transpose.c`` into
+"""Compiles ``oracle/matmul.c``, ``oracle/transpose.c`` and ``oracle/madd.c`` into
 ``oracle/_build/liboracle.so`` with gcc.
 
 Test infrastructure only.  Flags keep IEEE semantics (no fast-math, no FMA
@@ -11,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "matmul.c"), os.path.join(HERE, "transpose.c")]
+SOURCES = [os.path.join(HERE, "matmul.c"), os.path.join(HERE, "transpose.c"), os.path.join(HERE, "madd.c")]
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liboracle.so")
 

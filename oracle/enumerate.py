@@ -20,6 +20,10 @@ enumeration over a grid of machines and the whole program-parameter domain:
   holds one (by * s') x bx tile padded by one element per row: 4 * (by * s')
   * (bx + 1) bytes; threads bx * by.  One compiled program serves every
   4-byte element type.
+* Matrix-addition family (Section 1, Fig. 1 and Fig. 2): program parameters
+  bx (the paper's B1), by (B0), s; programs {} (s elements per thread) and
+  {gran} (one); no LDS, so the counters are registers per workgroup and
+  threads per workgroup (bx * by) only, the two machine parameters of Fig. 2.
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -41,12 +45,13 @@ import numpy as np
 from . import comprehensive as co
 
 F32, I32, BF16 = 0, 1, 2
-VALU, MFMA, TRANSPOSE = 0, 1, 2
+VALU, MFMA, TRANSPOSE, MADD = 0, 1, 2, 3
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 
 VALU_VARIANTS = (0, GRAN, GRAN | NOLDS, NOLDS)
 MFMA_VARIANTS = (0, SINGLE)
+MADD_VARIANTS = (0, GRAN)
 
 # machine grid: LDS bytes per workgroup, registers per workgroup, threads per workgroup
 LDS_GRID = (4 * 1024, 16 * 1024, 48 * 1024, 64 * 1024, 160 * 1024)
@@ -90,14 +95,14 @@ class InstanceData:
     def __init__(self, instances: List[dict]):
         self.by_key = {}
         for e in instances:
-            if e["family"] in (VALU, TRANSPOSE):
+            if e["family"] in (VALU, TRANSPOSE, MADD):
                 key = (e["family"], e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
             else:
                 key = (MFMA, e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"], e["wm"], e["wn"])
             self.by_key[key] = e
 
     def regs(self, family: int, dtype: int, variant: int, point: Tuple[int, ...]):
-        if family in (VALU, TRANSPOSE):
+        if family in (VALU, TRANSPOSE, MADD):
             bx, by, s = point
             kernel = variant & NOLDS
             outs = 1 if variant & GRAN else s
@@ -111,7 +116,7 @@ class InstanceData:
 
 
 def threads(family: int, point) -> int:
-    if family in (VALU, TRANSPOSE):
+    if family in (VALU, TRANSPOSE, MADD):
         return point[0] * point[1]
     return 64 * point[3] * point[4]
 
@@ -121,6 +126,8 @@ def lds(family: int, dtype: int, variant: int, point) -> int:
         return valu_lds(variant, *point)
     if family == TRANSPOSE:
         return transpose_lds(variant, *point)
+    if family == MADD:
+        return 0
     return mfma_lds(dtype, variant, point[0], point[1], point[2])
 
 
@@ -132,6 +139,8 @@ def fits(inst: InstanceData, family, dtype, variant, point, Z, V, T) -> bool:
 
 
 def variants(family: int):
+    if family == MADD:
+        return MADD_VARIANTS
     return MFMA_VARIANTS if family == MFMA else VALU_VARIANTS
 
 
@@ -151,6 +160,8 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
     its predecessor), 0, and one value above all of them, so the finite
     enumeration decides the same as integers without bound."""
     pts = [tuple(p) for p in points]
+    if family == MADD:
+        return _madd_family(dtype, pts, inst)
     if family == TRANSPOSE:
         program = ["bx", "by", "s"]
         strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
@@ -238,3 +249,40 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
         doms[name] = sorted({p[k] for p in pts})
     return co.Family(machine=["Z", "V", "T"], program=program, data=[], counters=counters,
                      strategies=strategies, domains=doms, tables=tables, points=pts)
+
+
+def _madd_family(dtype: int, pts, inst: InstanceData) -> co.Family:
+    """Fig. 2's system as a code fragment: counters r_V (registers per
+    workgroup, a table symbol per program) and r_T (bx * by), in that order;
+    one strategy, granularity reduction, which lowers r_V."""
+    program = ["bx", "by", "s"]
+    names = {0: "rho", GRAN: "rho_s1"}
+    counters = [co.Counter("r_V", "resource", "V",
+                           lambda applied: co.Poly.sym(names[GRAN if "gran" in applied else 0])),
+                co.Counter("r_T", "resource", "T", lambda applied: co.parse_poly("bx*by"))]
+    strategies = [co.Strategy("gran", False, frozenset({"r_V"}))]
+
+    def table_fn(var):
+        def f(env):
+            out = []
+            for p in zip(*[env[s] for s in program]):
+                r = inst.regs(MADD, dtype, var, tuple(int(x) for x in p))
+                out.append(r if r is not None else 1 << 40)
+            return np.array(out, dtype=np.int64)
+        return f
+
+    thresholds_v, thresholds_t = {0}, {0}
+    for p in pts:
+        for v in MADD_VARIANTS:
+            r = inst.regs(MADD, dtype, v, p)
+            if r is not None:
+                thresholds_v |= {r, max(r - 1, 0)}
+        t = threads(MADD, p)
+        thresholds_t |= {t, t - 1}
+    doms: Dict[str, list] = {"V": sorted(thresholds_v | {max(thresholds_v) + 1}),
+                             "T": sorted(thresholds_t | {max(thresholds_t) + 1})}
+    for k, name in enumerate(program):
+        doms[name] = sorted({p[k] for p in pts})
+    return co.Family(machine=["V", "T"], program=program, data=[], counters=counters,
+                     strategies=strategies, domains=doms, tables={names[v]: table_fn(v) for v in names},
+                     points=pts)

@@ -37,13 +37,14 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC,
           "-Wno-unused-command-line-argument"]
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
-HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp"]
+HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp",
+                "madd.cpp"]
 DEVICE_SOURCES = ["costmodel.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}
 DT_CTYPE = {F32: "float", I32: "int32_t"}
-FAM_VALU, FAM_MFMA, FAM_TR = 0, 1, 2
+FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA = 0, 1, 2, 3
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
@@ -51,6 +52,9 @@ MFMA_GROUPED = 2
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
 VALU_S = (1, 2, 4, 8)
+MA_BX = (64, 128, 256)
+MA_BY = (1, 2, 4)
+MA_S = (1, 2, 4, 8)
 TR_BX = (16, 32, 64)
 TR_BY = (4, 8, 16, 32)
 TR_S = (1, 2, 4, 8)
@@ -112,6 +116,16 @@ def instances():
                                  lds=0 if nolds else 4 * by * s * (bx + 1), tile_m=by * s, tile_n=bx,
                                  args="pkk::TrArgs a")
                     out.append(("transpose_bx%d" % bx, name, body, entry))
+    # matrix addition
+    for dt in (F32, I32):
+        for bx in MA_BX:
+            for by in MA_BY:
+                for s in MA_S:
+                    name = "pk_madd_%s_bx%d_by%d_s%d" % (DT_NAME[dt], bx, by, s)
+                    body = "pkk::madd<%s, %d, %d, %d>(a);" % (DT_CTYPE[dt], bx, by, s)
+                    entry = dict(family=FAM_MA, variant=0, dtype=dt, bx=bx, by=by, s=s, bk=0, bm=0, bn=0, wm=0,
+                                 wn=0, threads=bx * by, lds=0, tile_m=by, tile_n=bx * s, args="pkk::MaArgs a")
+                    out.append(("madd_%s" % DT_NAME[dt], name, body, entry))
     # persistent grouped instances of the MFMA programs up to 128 x 128
     gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
     for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):
@@ -143,7 +157,7 @@ def generate():
     for grp, items in sorted(groups.items()):
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
                  "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"',
-                 '#include "kernels/transpose.hpp"', ""]
+                 '#include "kernels/transpose.hpp"', '#include "kernels/madd.hpp"', ""]
         for name, body, entry in items:
             arg = entry.get("args", "pkk::MmArgs a")
             lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'

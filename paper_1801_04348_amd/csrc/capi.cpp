@@ -374,7 +374,7 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
               void *hip_stream) {
     if (!tbl) return fail(PK_ERR_INVALID_ARG, "null table");
     if (M < 0 || N < 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "negative dimension");
-    if (M > 0x7fffffff || N > 0x7fffffff || K > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "dimension above 2^31-1");
+    if (M > kMaxDim || N > kMaxDim || K > kMaxDim) return fail(PK_ERR_INVALID_ARG, "dimension above 2^31 - 2^16");
     if (dtype != PK_F32 && dtype != PK_I32 && dtype != PK_BF16) return fail(PK_ERR_UNSUPPORTED_DTYPE, "unknown dtype");
     if (M == 0 || N == 0) return PK_OK;
     if (!C || ldc < N) return fail(PK_ERR_INVALID_ARG, "null C or ldc < N");
@@ -386,8 +386,8 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
             if (rc != PK_OK) return rc;
             params_or_null = &sel;
         }
-        if (params_or_null->family == PK_FAMILY_TRANSPOSE)
-            return fail(PK_ERR_INVALID_ARG, "transposition parameters given to a product");
+        if (params_or_null->family != PK_FAMILY_VALU && params_or_null->family != PK_FAMILY_MFMA)
+            return fail(PK_ERR_INVALID_ARG, "parameters of a family that is not a product");
         pk_params q;
         const KernelEntry *e = nullptr;
         int rc = resolve(tbl, params_or_null, (int)dtype, &q, &e);

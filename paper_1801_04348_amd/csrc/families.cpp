@@ -29,6 +29,10 @@
 // the cached program: 4 * (by * s) * (bx + 1) -- one padded tile (the paper's
 // program caches a and c separately, 2 s B0 B1 words).
 //
+// Matrix-addition family (Section 1, Fig. 2): program parameters bx (B1), by
+// (B0), s (elements per work-item); counters, in gamma order, r_V and r_T
+// only (the two machine parameters of Fig. 2); strategy gran (sigma = {r_V}).
+//
 // MFMA family, program parameters bm, bn (output tile), bk (K tile), wm, wn
 // (wavefront grid).  Strategy:
 //   single (source; sigma = {r_Z, r_V}) one LDS stage instead of two (also no
@@ -50,6 +54,9 @@ struct MfmaPoint {
 const int kValuB[] = {4, 8, 16, 32};
 const int kValuS[] = {1, 2, 4, 8};
 
+const int kMaBx[] = {64, 128, 256};
+const int kMaBy[] = {1, 2, 4};
+const int kMaS[] = {1, 2, 4, 8};
 const int kTrBx[] = {16, 32, 64};
 const int kTrBy[] = {4, 8, 16, 32};
 const int kTrS[] = {1, 2, 4, 8};
@@ -67,14 +74,18 @@ struct Syms {
     int Z, V, T;
 };
 
-Syms add_machine(Family &f) {
-    for (const char *n : {"Z", "V", "T"}) {
-        f.sym_names.push_back(n);
+// Machine symbols Z (LDS bytes), V (registers) and T (work-items) per
+// workgroup; a family that uses no LDS has no Z.
+Syms add_machine(Family &f, bool lds = true) {
+    const int first = lds ? 0 : 1;
+    const char *names[] = {"Z", "V", "T"};
+    for (int i = first; i < 3; ++i) {
+        f.sym_names.push_back(names[i]);
         f.sym_kind.push_back(SYM_MACHINE);
         f.lo.push_back(0);
         f.hi.push_back(INT64_MAX / 4);
     }
-    return Syms{0, 1, 2};
+    return lds ? Syms{0, 1, 2} : Syms{-1, 0, 1};
 }
 
 int add_sym(Family &f, const char *name, int kind) {
@@ -109,7 +120,7 @@ int64_t regs_per_block(const KernelResources &r, int threads, int wave) {
 
 Family matmul_family(int family, int dtype) {
     Family f;
-    Syms m = add_machine(f);
+    Syms m = add_machine(f, family != PK_FAMILY_MADD);
     if (family == PK_FAMILY_VALU) {
         if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("VALU family: f32 and i32 only");
         const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
@@ -144,6 +155,26 @@ Family matmul_family(int family, int dtype) {
             if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
             if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
             return table_regs(PK_FAMILY_VALU, variant, dtype, pt, 64);
+        };
+        return f;
+    }
+    if (family == PK_FAMILY_MADD) {
+        if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("matrix addition: f32 and i32 only");
+        const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
+                  s = add_sym(f, "s", SYM_PROGRAM);
+        const int rho = add_sym(f, "rho", SYM_TABLE), rho1 = add_sym(f, "rho_s1", SYM_TABLE);
+        f.point_syms = {bx, by, s};
+        for (int x : kMaBx)
+            for (int y : kMaBy)
+                for (int z : kMaS) f.points.push_back({x, y, z});
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) { return S((ap & PK_VALU_GRAN) ? rho1 : rho); };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return S(bx) * S(by); };
+        f.counters = {rv, rt};
+        f.strategies = {StrategyDef{"gran", false, 0b01u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            return table_regs(PK_FAMILY_MADD, sym == rho1 ? PK_VALU_GRAN : 0, dtype, pt, 64);
         };
         return f;
     }
@@ -214,7 +245,7 @@ Family matmul_family(int family, int dtype) {
 }
 
 bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
-    if (family == PK_FAMILY_TRANSPOSE) {
+    if (family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         *pt = {p.bx, p.by, p.s};
         return true;
     }
@@ -233,7 +264,7 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
     p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
-    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
+    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         p->bx = (int32_t)pt[0];
         p->by = (int32_t)pt[1];
         p->s = (int32_t)pt[2];
@@ -249,7 +280,7 @@ void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
 
 std::vector<int64_t> machine_values(const Family &fam, const pk_machine &m) {
     std::vector<int64_t> v(fam.sym_names.size(), 0);
-    v[fam.sym("Z")] = m.lds_block;
+    if (fam.sym("Z") >= 0) v[fam.sym("Z")] = m.lds_block;
     v[fam.sym("V")] = m.regs_block;
     v[fam.sym("T")] = m.max_threads_block;
     return v;
@@ -271,7 +302,7 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     int kind = 0;
     std::vector<int64_t> q = pt;
     if (family == PK_FAMILY_TRANSPOSE) dtype = PK_F32;  // a bit copy: one instance serves every 4-byte type
-    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
+    if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         if (variant & PK_VALU_GRAN) q[2] = 1;
         kind = variant & PK_VALU_NOLDS;
     } else {
@@ -279,7 +310,7 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     }
     for (const auto &e : registry()) {
         if (e.family != family || e.dtype != dtype || e.variant != kind) continue;
-        if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE) {
+        if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
             if (e.bx == q[0] && e.by == q[1] && e.s == q[2]) return &e;
         } else {
             if (e.bm == q[0] && e.bn == q[1] && e.bk == q[2] && e.wm == q[3] && e.wn == q[4]) return &e;

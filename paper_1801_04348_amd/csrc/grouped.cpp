@@ -90,7 +90,7 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
         plan->chosen.assign(G, pk_params{});
         std::vector<std::vector<Candidate>> okc(G);
         for (int g = 0; g < G; ++g) {
-            if (M[g] < 0 || N[g] < 0 || K[g] < 0 || M[g] > 0x7fffffff || N[g] > 0x7fffffff || K[g] > 0x7fffffff)
+            if (M[g] < 0 || N[g] < 0 || K[g] < 0 || M[g] > kMaxDim || N[g] > kMaxDim || K[g] > kMaxDim)
                 return fail(PK_ERR_INVALID_ARG, "bad size in product " + std::to_string(g));
             if (M[g] == 0 || N[g] == 0) continue;
             if (!C[g] || ldc[g] < N[g] || (K[g] > 0 && (!A[g] || !B[g] || lda[g] < K[g] || ldb[g] < N[g])))

@@ -23,6 +23,11 @@
 
 namespace pk {
 
+// Largest M, N or K accepted: kernels index rows and columns in 32-bit
+// integers, and a tile rounded up past the last row or column must still fit.
+constexpr int64_t kMaxDim = 0x7fff0000;
+
+
 // ------------------------------------------------------------------ errors
 int fail(int code, const std::string &msg);  // stores msg for pk_last_error, returns code
 void clear_error();

@@ -143,7 +143,7 @@ int pk_transpose(const pk_table *tbl, const pk_params *params_or_null, pk_dtype 
                  void *C, int64_t ldc, int64_t M, int64_t N, void *hip_stream) {
     if (!tbl) return fail(PK_ERR_INVALID_ARG, "null table");
     if (dtype != PK_F32 && dtype != PK_I32) return fail(PK_ERR_UNSUPPORTED_DTYPE, "transposition: 4-byte elements");
-    if (M < 0 || N < 0 || M > 0x7fffffff || N > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "bad dimension");
+    if (M < 0 || N < 0 || M > kMaxDim || N > kMaxDim) return fail(PK_ERR_INVALID_ARG, "bad dimension");
     if (M == 0 || N == 0) return PK_OK;
     if (!A || !C || lda < N || ldc < M) return fail(PK_ERR_INVALID_ARG, "null pointer or leading dimension too small");
     pk_params sel;

@@ -34,7 +34,7 @@ PK_ERR_BUFFER_TOO_SMALL = -7
 PK_ERR_PARSE = -8
 
 PK_F32, PK_I32, PK_BF16 = 0, 1, 2
-PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE = 0, 1, 2
+PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD = 0, 1, 2, 3
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
@@ -125,6 +125,10 @@ def lib():
         L.pk_transpose.restype = i32
         L.pk_select_transpose.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_transpose.restype = i32
+        L.pk_madd.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
+        L.pk_madd.restype = i32
+        L.pk_select_madd.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_madd.restype = i32
         L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
         L.pk_kernel_name.restype = ctypes.c_char_p
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -281,6 +285,24 @@ def pk_transpose(tbl: Table, p, dtype, A, C, stream=None):
     c, ldc = _ptr_ld(C)
     _check(lib().pk_transpose(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
                               c, max(ldc, M), M, N, _stream(stream)))
+
+
+def pk_select_madd(tbl: Table, dtype, M: int, N: int, policy: int = PK_POLICY_CASE) -> pk_params:
+    out = pk_params()
+    _check(lib().pk_select_madd(tbl.handle, _dt(dtype), M, N, policy, ctypes.byref(out)))
+    return out
+
+
+def pk_madd(tbl: Table, p, dtype, A, B, C, stream=None):
+    """C = A + B on the device (f32 or wrapping i32); A, B, C: (M, N)."""
+    M, N = A.shape
+    if tuple(B.shape) != (M, N) or tuple(C.shape) != (M, N):
+        raise ValueError("A, B and C must have the same shape")
+    a, lda = _ptr_ld(A)
+    b, ldb = _ptr_ld(B)
+    c, ldc = _ptr_ld(C)
+    _check(lib().pk_madd(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
+                         b, max(ldb, N), c, max(ldc, N), M, N, _stream(stream)))
 
 
 def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:

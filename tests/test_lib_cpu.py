@@ -123,6 +123,8 @@ def test_lds_counter_equals_compiled_lds(gfx_desc):
             assert e["lds_bytes"] == en.valu_lds(e["variant"], e["bx"], e["by"], e["s"])
         elif e["family"] == en.TRANSPOSE:
             assert e["lds_bytes"] == en.transpose_lds(e["variant"], e["bx"], e["by"], e["s"])
+        elif e["family"] == en.MADD:
+            assert e["lds_bytes"] == 0
         else:
             assert e["lds_bytes"] == en.mfma_lds(e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"])
         assert e["scratch"] == 0, e["name"]   # no register spills in any instance
@@ -195,7 +197,8 @@ def test_optimality_definition_3_iv(gfx_desc):
     # left unapplied (so none can lower it further)
     sigma = {0: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
              1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()},
-             2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
+             2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
+             3: {"r_V": {"gran"}, "r_T": set()}}
     for part in gfx_desc["parts"]:
         for counter, strategies in sigma[part["family"]].items():
             assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
@@ -270,3 +273,38 @@ def test_matmul_argument_errors_without_gpu(gfx_table):
     bad = pk.params(family=pk.PK_FAMILY_MFMA, bm=64, bn=64, bk=32, wm=2, wn=2)
     rc = L.pk_matmul(gfx_table.handle, bad, pk.PK_I32, 16, 4, 16, 4, 16, 4, 4, 4, 4, 0, None)
     assert rc == pk.PK_ERR_UNSUPPORTED_DTYPE
+
+
+def test_madd_table_has_fig2_shape():
+    # Section 1, Fig. 2: two leaves; the unmodified program where its
+    # registers fit, else the one-element-per-thread program; both bounded by
+    # bx*by <= T.  Machine symbols: V and T only (no LDS in the family).
+    d = pk.pk_case_table_describe(pk.pk_case_table_build(0, machines.gfx950()))
+    for part in [p for p in d["parts"] if p["family"] == pk.PK_FAMILY_MADD]:
+        assert part["counters"] == ["r_V", "r_T"] and part["strategies"] == ["gran"]
+        leaves = part["solution"]["leaves"]
+        assert [l["applied"] for l in leaves] == [[], ["gran"]]
+        texts = [{c["text"] for c in l["system"]} for l in leaves]
+        assert {"rho <= V", "bx*by <= T"} <= texts[0]
+        assert {"V < rho", "rho_s1 <= V", "bx*by <= T"} <= texts[1]
+        assert not any("Z" in t for s in texts for t in s)
+        # granularity reduction lowers (or keeps) the register count, as the
+        # paper's 14 -> 10 example
+        assert all(a >= b for a, b in zip(part["tables"]["rho"], part["tables"]["rho_s1"]))
+
+
+def test_madd_small_register_file_takes_gran_leaf():
+    m = machines.grid_machine(65536, 16384, 1024)
+    t = pk.pk_case_table_build(0, m)
+    leaf, var = pk.pk_case_table_lookup(t, "f32", pk.params(family=pk.PK_FAMILY_MADD, bx=256, by=4, s=8))
+    assert var == pk.PK_VALU_GRAN and leaf == 1        # 40960 registers > V, 16384 after reduction
+    leaf, var = pk.pk_case_table_lookup(t, "f32", pk.params(family=pk.PK_FAMILY_MADD, bx=64, by=1, s=8))
+    assert var == 0 and leaf == 0
+    with pytest.raises(pk.PkError) as e:                # 1024 < bx*by: no leaf
+        pk.pk_case_table_lookup(pk.pk_case_table_build(0, machines.grid_machine(65536, 131072, 512)), "i32",
+                                pk.params(family=pk.PK_FAMILY_MADD, bx=256, by=4, s=1))
+    assert e.value.code == pk.PK_ERR_NO_FEASIBLE_BRANCH
+    p = pk.pk_select_madd(t, "i32", 1000, 3000)
+    assert p.family == pk.PK_FAMILY_MADD and p.leaf in (0, 1)
+    with pytest.raises(pk.PkError):
+        pk.pk_select_madd(t, "bf16", 10, 10)
