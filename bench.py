@@ -164,6 +164,34 @@ def madd_section(tbl, pk, torch, inputs, n=16384, reps=10):
     return out
 
 
+def jacobi_section(tbl, pk, torch, inputs, steps=4, reps=10):
+    """1D Jacobi (Section 5, Fig. 6): four time steps at the paper's length
+    2^15 + 2 (Table 2; launch-bound: microseconds per step) and at 2^28 + 2
+    (HBM-bound), int32; CASE pick and exhaustively-best leaf, in GB/s of
+    compulsory traffic (8 bytes per interior point and step) against 8 TB/s."""
+    out = {"steps": steps}
+    for label, N in (("n_2^15+2", 2 ** 15 + 2), ("n_2^28+2", 2 ** 28 + 2)):
+        a = inputs.small_int_i32((2 * N,), seed=0).cuda()
+        bytes_ = 8 * (N - 2) * steps
+        row = {"bytes": bytes_}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            p = pk.pk_select_jacobi1d(tbl, "i32", N, pol)
+            pk.pk_jacobi1d(tbl, p, "i32", a, steps)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pk.pk_jacobi1d(tbl, p, "i32", a, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) / reps * 1e-3
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, "i32"), "us": round(s * 1e6, 2),
+                         "gbps": round(bytes_ / s / 1e9, 1), "frac_hbm": round(bytes_ / s / 8e12, 4)}
+        out[label] = row
+        del a
+    return out
+
+
 def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
     """Transposition of an order-2^14 float32 matrix (the paper's Table 3
     size): the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
@@ -194,7 +222,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--policy", choices=["auto", "case", "learned"], default="auto",
                     help="auto: the learned cost model when one for this machine is shipped, else the case table")
-    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition, 1D Jacobi")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
@@ -377,6 +405,7 @@ def main():
 
     transpose = None if args.no_grouped else transpose_section(tbl, pk, torch, inputs)
     madd = None if args.no_grouped else madd_section(tbl, pk, torch, inputs)
+    jacobi = None if args.no_grouped else jacobi_section(tbl, pk, torch, inputs)
     grouped = None
     if not args.no_grouped:
         grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
@@ -390,7 +419,7 @@ def main():
                       "parallelism": "none (1 GPU)"},
            "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
            "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "transpose": transpose,
-           "madd": madd,
+           "madd": madd, "jacobi": jacobi,
            "roofline": roofline,
            "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
     if not args.no_cpu_baseline:

@@ -83,7 +83,8 @@ typedef struct {
 #define PK_FAMILY_MFMA 1  /* LDS-tiled matrix-core kernel, f32 and bf16 */
 #define PK_FAMILY_TRANSPOSE 2 /* matrix transposition (Section 5.2, Fig. 7), 4-byte elements */
 #define PK_FAMILY_MADD 3      /* matrix addition (Section 1, Fig. 1 and Fig. 2), f32 and i32 */
-#define PK_NUM_FAMILIES 4
+#define PK_FAMILY_JACOBI 4    /* 1D Jacobi time step (Section 5, Fig. 6, Table 2), f32 and i32 */
+#define PK_NUM_FAMILIES 5
 
 /* Strategy bits of the VALU family (a variant is the set of strategies applied):
  * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
@@ -113,7 +114,11 @@ typedef struct {
  *   a workgroup moves a (by * s) x bx tile of A.
  * Matrix-addition family: bx = work-items along a row (Fig. 2's B1), by =
  *   rows per workgroup (B0), s = elements per work-item (2 in Fig. 2's K1);
- *   strategy bit PK_VALU_GRAN (one element per work-item, Fig. 2's K2). */
+ *   strategy bit PK_VALU_GRAN (one element per work-item, Fig. 2's K2).
+ * 1D Jacobi family: bx = work-items per workgroup (Fig. 6's B), s = points
+ *   per work-item (s); by unused (0 or 1); strategy bits as the VALU family
+ *   (PK_VALU_GRAN: s = 1, the second case; PK_VALU_NOLDS: no LDS caching,
+ *   the third case). */
 typedef struct {
     int32_t family;
     int32_t leaf;
@@ -282,6 +287,24 @@ int pk_select_transpose(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t 
 int pk_madd(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, const void *A, int64_t lda,
             const void *B, int64_t ldb, void *C, int64_t ldc, int64_t M, int64_t N, void *hip_stream);
 int pk_select_madd(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int policy, pk_params *out);
+
+/* ------------------------------------------------------------------ 1D Jacobi */
+/* `steps` time steps of the three-point stencil of Section 5, Fig. 6, in
+ * place on a device array a of 2N elements holding two copies of a length-N
+ * vector: step t writes the interior (indices 1 .. N-2) of the second copy
+ * from the first when t is even, of the first from the second when t is odd
+ * (so the result sits in the second copy after an odd number of steps, in
+ * the first after an even number); elements 0, N-1, N and 2N-1 are never
+ * written.  Each point becomes (left + centre + right) / 3: i32 sums wrap
+ * modulo 2^32 and the quotient truncates toward zero; f32 rounds after each
+ * addition (left to right) and after the correctly rounded division.  One
+ * kernel launch per step, queued on hip_stream (asynchronous).  N >= 2
+ * (N = 2 or steps = 0: nothing to do), steps >= 0.  params_or_null: family
+ * PK_FAMILY_JACOBI, resolved as in pk_matmul (NULL: the CASE choice).
+ * Errors as pk_transpose. */
+int pk_jacobi1d(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, void *a, int64_t N,
+                int64_t steps, void *hip_stream);
+int pk_select_jacobi1d(const pk_table *tbl, pk_dtype dtype, int64_t N, int policy, pk_params *out);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */

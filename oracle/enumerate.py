@@ -24,6 +24,10 @@ enumeration over a grid of machines and the whole program-parameter domain:
   bx (the paper's B1), by (B0), s; programs {} (s elements per thread) and
   {gran} (one); no LDS, so the counters are registers per workgroup and
   threads per workgroup (bx * by) only, the two machine parameters of Fig. 2.
+* 1D Jacobi family (Section 5, Fig. 6): program parameters B (work-items
+  per workgroup) and s (points per work-item); programs as in the VALU
+  family; the cached program holds the tile's s' * B inputs and one halo
+  point on each side: 4 * (s' * B + 2) bytes; threads B.
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -45,7 +49,7 @@ import numpy as np
 from . import comprehensive as co
 
 F32, I32, BF16 = 0, 1, 2
-VALU, MFMA, TRANSPOSE, MADD = 0, 1, 2, 3
+VALU, MFMA, TRANSPOSE, MADD, JACOBI = 0, 1, 2, 3, 4
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 
@@ -80,6 +84,13 @@ def transpose_lds(variant: int, bx: int, by: int, s: int) -> int:
     return 4 * by * outs * (bx + 1)
 
 
+def jacobi_lds(variant: int, b: int, s: int) -> int:
+    if variant & NOLDS:
+        return 0
+    outs = 1 if variant & GRAN else s
+    return 4 * (outs * b + 2)
+
+
 def mfma_lds(dtype: int, variant: int, bm: int, bn: int, bk: int) -> int:
     stages = 1 if variant & SINGLE else 2
     if dtype == F32:
@@ -95,14 +106,18 @@ class InstanceData:
     def __init__(self, instances: List[dict]):
         self.by_key = {}
         for e in instances:
-            if e["family"] in (VALU, TRANSPOSE, MADD):
+            if e["family"] in (VALU, TRANSPOSE, MADD, JACOBI):
                 key = (e["family"], e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
             else:
                 key = (MFMA, e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"], e["wm"], e["wn"])
             self.by_key[key] = e
 
     def regs(self, family: int, dtype: int, variant: int, point: Tuple[int, ...]):
-        if family in (VALU, TRANSPOSE, MADD):
+        if family == JACOBI:
+            b, s = point
+            outs = 1 if variant & GRAN else s
+            e = self.by_key.get((JACOBI, dtype, variant & NOLDS, b, 1, outs))
+        elif family in (VALU, TRANSPOSE, MADD):
             bx, by, s = point
             kernel = variant & NOLDS
             outs = 1 if variant & GRAN else s
@@ -116,6 +131,8 @@ class InstanceData:
 
 
 def threads(family: int, point) -> int:
+    if family == JACOBI:
+        return point[0]
     if family in (VALU, TRANSPOSE, MADD):
         return point[0] * point[1]
     return 64 * point[3] * point[4]
@@ -128,6 +145,8 @@ def lds(family: int, dtype: int, variant: int, point) -> int:
         return transpose_lds(variant, *point)
     if family == MADD:
         return 0
+    if family == JACOBI:
+        return jacobi_lds(variant, *point)
     return mfma_lds(dtype, variant, point[0], point[1], point[2])
 
 
@@ -162,7 +181,26 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
     pts = [tuple(p) for p in points]
     if family == MADD:
         return _madd_family(dtype, pts, inst)
-    if family == TRANSPOSE:
+    if family == JACOBI:
+        program = ["B", "s"]
+        strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
+                      co.Strategy("nolds", False, frozenset({"r_Z", "r_V"}))]
+        names = {0: "rho_tiled", GRAN: "rho_tiled_s1", NOLDS: "rho_direct", GRAN | NOLDS: "rho_direct_s1"}
+
+        def lds_poly(applied):
+            a = set(applied)
+            if "nolds" in a:
+                return co.Poly.const(0)
+            if "gran" in a:
+                return co.parse_poly("4*B + 8")
+            return co.parse_poly("4*s*B + 8")
+
+        def bits(applied):
+            a = set(applied)
+            return (GRAN if "gran" in a else 0) | (NOLDS if "nolds" in a else 0)
+
+        thr = co.parse_poly("B")
+    elif family == TRANSPOSE:
         program = ["bx", "by", "s"]
         strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
                       co.Strategy("nolds", False, frozenset({"r_Z", "r_V"}))]

@@ -38,13 +38,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE,
           "-Wno-unused-command-line-argument"]
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
 HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp",
-                "madd.cpp"]
+                "madd.cpp", "jacobi.cpp"]
 DEVICE_SOURCES = ["costmodel.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}
 DT_CTYPE = {F32: "float", I32: "int32_t"}
-FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA = 0, 1, 2, 3
+FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA = 0, 1, 2, 3, 4
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
@@ -52,6 +52,8 @@ MFMA_GROUPED = 2
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
 VALU_S = (1, 2, 4, 8)
+JA_B = (16, 32, 64, 128, 256, 512, 1024)
+JA_S = (1, 2, 4, 8)
 MA_BX = (64, 128, 256)
 MA_BY = (1, 2, 4)
 MA_S = (1, 2, 4, 8)
@@ -126,6 +128,19 @@ def instances():
                     entry = dict(family=FAM_MA, variant=0, dtype=dt, bx=bx, by=by, s=s, bk=0, bm=0, bn=0, wm=0,
                                  wn=0, threads=bx * by, lds=0, tile_m=by, tile_n=bx * s, args="pkk::MaArgs a")
                     out.append(("madd_%s" % DT_NAME[dt], name, body, entry))
+    # 1D Jacobi: cached (LDS) and direct programs
+    for dt in (F32, I32):
+        for nolds in (False, True):
+            for b in JA_B:
+                for s in JA_S:
+                    kind = "direct" if nolds else "tiled"
+                    name = "pk_jacobi_%s_%s_b%d_s%d" % (kind, DT_NAME[dt], b, s)
+                    body = "pkk::jacobi_%s<%s, %d, %d>(a);" % (kind, DT_CTYPE[dt], b, s)
+                    lds = 0 if nolds else 4 * (s * b + 2)
+                    entry = dict(family=FAM_JA, variant=VALU_NOLDS if nolds else 0, dtype=dt, bx=b, by=1, s=s, bk=0,
+                                 bm=0, bn=0, wm=0, wn=0, threads=b, lds=lds, tile_m=1, tile_n=s * b,
+                                 args="pkk::JaArgs a")
+                    out.append(("jacobi_%s" % DT_NAME[dt], name, body, entry))
     # persistent grouped instances of the MFMA programs up to 128 x 128
     gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
     for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):
@@ -157,7 +172,8 @@ def generate():
     for grp, items in sorted(groups.items()):
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
                  "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"',
-                 '#include "kernels/transpose.hpp"', '#include "kernels/madd.hpp"', ""]
+                 '#include "kernels/transpose.hpp"', '#include "kernels/madd.hpp"',
+                 '#include "kernels/jacobi.hpp"', ""]
         for name, body, entry in items:
             arg = entry.get("args", "pkk::MmArgs a")
             lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'

@@ -33,6 +33,12 @@
 // (B0), s (elements per work-item); counters, in gamma order, r_V and r_T
 // only (the two machine parameters of Fig. 2); strategy gran (sigma = {r_V}).
 //
+// 1D Jacobi family (Section 5, Fig. 6): program parameters B (work-items per
+// workgroup, stored as bx) and s (points per work-item); strategies gran and
+// nolds as in the VALU family.  LDS bytes of the cached program:
+// 4 * (s * B + 2) -- the tile's inputs with one halo point on each side (the
+// paper's program caches inputs and outputs, 2 s B + 2 words).
+//
 // MFMA family, program parameters bm, bn (output tile), bk (K tile), wm, wn
 // (wavefront grid).  Strategy:
 //   single (source; sigma = {r_Z, r_V}) one LDS stage instead of two (also no
@@ -57,6 +63,8 @@ const int kValuS[] = {1, 2, 4, 8};
 const int kMaBx[] = {64, 128, 256};
 const int kMaBy[] = {1, 2, 4};
 const int kMaS[] = {1, 2, 4, 8};
+const int kJaB[] = {16, 32, 64, 128, 256, 512, 1024};
+const int kJaS[] = {1, 2, 4, 8};
 const int kTrBx[] = {16, 32, 64};
 const int kTrBy[] = {4, 8, 16, 32};
 const int kTrS[] = {1, 2, 4, 8};
@@ -158,6 +166,39 @@ Family matmul_family(int family, int dtype) {
         };
         return f;
     }
+    if (family == PK_FAMILY_JACOBI) {
+        if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("1D Jacobi: f32 and i32 only");
+        const int b = add_sym(f, "B", SYM_PROGRAM), s = add_sym(f, "s", SYM_PROGRAM);
+        const int rho_t = add_sym(f, "rho_tiled", SYM_TABLE), rho_t1 = add_sym(f, "rho_tiled_s1", SYM_TABLE),
+                  rho_d = add_sym(f, "rho_direct", SYM_TABLE), rho_d1 = add_sym(f, "rho_direct_s1", SYM_TABLE);
+        f.point_syms = {b, s};
+        for (int x : kJaB)
+            for (int z : kJaS) f.points.push_back({x, z});
+        const Poly lds_full = P(4) * (S(s) * S(b) + P(2));
+        const Poly lds_g1 = P(4) * (S(b) + P(2));
+        CounterDef rz{"r_Z", false, m.Z, nullptr};
+        rz.value = [=](uint32_t ap) {
+            if (ap & PK_VALU_NOLDS) return P(0);
+            if (ap & PK_VALU_GRAN) return lds_g1;
+            return lds_full;
+        };
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) {
+            const bool g = ap & PK_VALU_GRAN, d = ap & PK_VALU_NOLDS;
+            return S(d ? (g ? rho_d1 : rho_d) : (g ? rho_t1 : rho_t));
+        };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return S(b); };
+        f.counters = {rz, rv, rt};
+        f.strategies = {StrategyDef{"gran", false, 0b011u}, StrategyDef{"nolds", false, 0b011u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            int variant = 0;
+            if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
+            if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
+            return table_regs(PK_FAMILY_JACOBI, variant, dtype, pt, 64);
+        };
+        return f;
+    }
     if (family == PK_FAMILY_MADD) {
         if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("matrix addition: f32 and i32 only");
         const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
@@ -245,6 +286,11 @@ Family matmul_family(int family, int dtype) {
 }
 
 bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
+    if (family == PK_FAMILY_JACOBI) {
+        if (p.by != 0 && p.by != 1) return false;
+        *pt = {p.bx, p.s};
+        return true;
+    }
     if (family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         *pt = {p.bx, p.by, p.s};
         return true;
@@ -264,6 +310,12 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
     p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
+    if (family == PK_FAMILY_JACOBI) {
+        p->bx = (int32_t)pt[0];
+        p->by = 1;
+        p->s = (int32_t)pt[1];
+        return;
+    }
     if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         p->bx = (int32_t)pt[0];
         p->by = (int32_t)pt[1];
@@ -302,6 +354,14 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     int kind = 0;
     std::vector<int64_t> q = pt;
     if (family == PK_FAMILY_TRANSPOSE) dtype = PK_F32;  // a bit copy: one instance serves every 4-byte type
+    if (family == PK_FAMILY_JACOBI) {
+        const int64_t s = (variant & PK_VALU_GRAN) ? 1 : pt[1];
+        for (const auto &e : registry())
+            if (e.family == family && e.dtype == dtype && e.variant == (variant & PK_VALU_NOLDS) && e.bx == pt[0] &&
+                e.s == s)
+                return &e;
+        return nullptr;
+    }
     if (family == PK_FAMILY_VALU || family == PK_FAMILY_TRANSPOSE || family == PK_FAMILY_MADD) {
         if (variant & PK_VALU_GRAN) q[2] = 1;
         kind = variant & PK_VALU_NOLDS;

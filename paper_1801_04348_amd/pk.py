@@ -34,7 +34,7 @@ PK_ERR_BUFFER_TOO_SMALL = -7
 PK_ERR_PARSE = -8
 
 PK_F32, PK_I32, PK_BF16 = 0, 1, 2
-PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD = 0, 1, 2, 3
+PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_JACOBI = 0, 1, 2, 3, 4
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
@@ -129,6 +129,10 @@ def lib():
         L.pk_madd.restype = i32
         L.pk_select_madd.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_madd.restype = i32
+        L.pk_jacobi1d.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, i64, vp]
+        L.pk_jacobi1d.restype = i32
+        L.pk_select_jacobi1d.argtypes = [vp, i32, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_jacobi1d.restype = i32
         L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
         L.pk_kernel_name.restype = ctypes.c_char_p
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -303,6 +307,21 @@ def pk_madd(tbl: Table, p, dtype, A, B, C, stream=None):
     c, ldc = _ptr_ld(C)
     _check(lib().pk_madd(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
                          b, max(ldb, N), c, max(ldc, N), M, N, _stream(stream)))
+
+
+def pk_select_jacobi1d(tbl: Table, dtype, N: int, policy: int = PK_POLICY_CASE) -> pk_params:
+    out = pk_params()
+    _check(lib().pk_select_jacobi1d(tbl.handle, _dt(dtype), N, policy, ctypes.byref(out)))
+    return out
+
+
+def pk_jacobi1d(tbl: Table, p, dtype, a, steps: int, stream=None):
+    """`steps` time steps in place on the device array a of 2N elements (two
+    copies of the length-N vector), one launch per step."""
+    if a.dim() != 1 or a.numel() % 2 or not a.is_contiguous():
+        raise ValueError("a must be a contiguous 1-D array of even length")
+    _check(lib().pk_jacobi1d(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype),
+                             ctypes.c_void_p(a.data_ptr()), a.numel() // 2, steps, _stream(stream)))
 
 
 def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:

@@ -125,6 +125,8 @@ def test_lds_counter_equals_compiled_lds(gfx_desc):
             assert e["lds_bytes"] == en.transpose_lds(e["variant"], e["bx"], e["by"], e["s"])
         elif e["family"] == en.MADD:
             assert e["lds_bytes"] == 0
+        elif e["family"] == en.JACOBI:
+            assert e["lds_bytes"] == en.jacobi_lds(e["variant"], e["bx"], e["s"])
         else:
             assert e["lds_bytes"] == en.mfma_lds(e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"])
         assert e["scratch"] == 0, e["name"]   # no register spills in any instance
@@ -198,7 +200,8 @@ def test_optimality_definition_3_iv(gfx_desc):
     sigma = {0: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
              1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()},
              2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
-             3: {"r_V": {"gran"}, "r_T": set()}}
+             3: {"r_V": {"gran"}, "r_T": set()},
+             4: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
     for part in gfx_desc["parts"]:
         for counter, strategies in sigma[part["family"]].items():
             assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
@@ -308,3 +311,30 @@ def test_madd_small_register_file_takes_gran_leaf():
     assert p.family == pk.PK_FAMILY_MADD and p.leaf in (0, 1)
     with pytest.raises(pk.PkError):
         pk.pk_select_madd(t, "bf16", 10, 10)
+
+
+def test_jacobi_table_follows_fig6_cases():
+    # Section 5, Fig. 6: the cached program while its LDS fits, granularity 1
+    # while that fits, then no LDS; here LDS bytes 4*(s*B + 2) and 4*(B + 2)
+    V, T = 131072, 1024
+    p = pk.params(family=pk.PK_FAMILY_JACOBI, bx=256, s=8)
+    for Z, want in ((65536, 0), (8200, 0), (8199, pk.PK_VALU_GRAN), (1032, pk.PK_VALU_GRAN),
+                    (1031, pk.PK_VALU_GRAN | pk.PK_VALU_NOLDS), (0, pk.PK_VALU_GRAN | pk.PK_VALU_NOLDS)):
+        t = pk.pk_case_table_build(0, machines.grid_machine(Z, V, T))
+        for dt in ("i32", "f32"):
+            leaf, var = pk.pk_case_table_lookup(t, dt, p)
+            assert var == want, (Z, dt, var)
+    d = pk.pk_case_table_describe(pk.pk_case_table_build(0, machines.gfx950()))
+    for part in [q for q in d["parts"] if q["family"] == pk.PK_FAMILY_JACOBI]:
+        leaves = [(tuple(l["applied"]), {c["text"] for c in l["system"]}) for l in part["solution"]["leaves"]]
+        # the three printed cases, each as one leaf (register leaves besides)
+        assert any(a == () and "4*B*s + 8 <= Z" in t for a, t in leaves)
+        assert any(a == ("gran",) and {"Z < 4*B*s + 8", "4*B + 8 <= Z"} <= t for a, t in leaves)
+        assert any(a == ("gran", "nolds") and "Z < 4*B + 8" in t for a, t in leaves)
+    t = pk.pk_case_table_build(0, machines.gfx950())
+    q = pk.pk_select_jacobi1d(t, "i32", 2 ** 15 + 2)
+    assert q.family == pk.PK_FAMILY_JACOBI and q.by == 1
+    with pytest.raises(pk.PkError):
+        pk.pk_select_jacobi1d(t, "i32", 1)
+    with pytest.raises(pk.PkError):
+        pk.pk_case_table_lookup(t, "i32", pk.params(family=pk.PK_FAMILY_JACOBI, bx=256, by=2, s=1))
