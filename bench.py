@@ -192,6 +192,43 @@ def jacobi_section(tbl, pk, torch, inputs, steps=4, reps=10):
     return out
 
 
+def polydiv_section(tbl, pk, torch, reps=5):
+    """Polynomial division modulo 2^31 - 1 (Section 5, Fig. 8, Table 4): a
+    dividend of N = M + 100 coefficients by a monic divisor of degree M, for
+    M = 2^13, 2^14, 2^15; CASE pick and exhaustively-best leaf, in
+    microseconds per division and GB/s of compulsory traffic (a, b read and
+    a written once per step: 12 bytes per divisor coefficient and step)."""
+    P = 2147483647
+    out = {"modulus": P}
+    g = torch.Generator().manual_seed(0)
+    for e in (13, 14, 15):
+        M = 2 ** e
+        N = M + 100
+        a0 = torch.randint(0, P, (N,), generator=g, dtype=torch.int64).to(torch.int32).cuda()
+        b = torch.randint(0, P, (M,), generator=g, dtype=torch.int64).to(torch.int32).cuda()
+        a = a0.clone()
+        bytes_ = 12 * M * (N - M)
+        row = {"N": N, "bytes": bytes_}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            p = pk.pk_select_polydiv(tbl, N, M, pol)
+            pk.pk_polydiv(tbl, p, a, b, P)
+            ts = []
+            for _ in range(reps):
+                a.copy_(a0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pk.pk_polydiv(tbl, p, a, b, P)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            s = sorted(ts)[len(ts) // 2]
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, "i32"), "us": round(s * 1e6, 1),
+                         "gbps": round(bytes_ / s / 1e9, 1), "frac_hbm": round(bytes_ / s / 8e12, 5)}
+        out["M_2^%d" % e] = row
+    return out
+
+
 def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
     """Transposition of an order-2^14 float32 matrix (the paper's Table 3
     size): the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
@@ -222,7 +259,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--policy", choices=["auto", "case", "learned"], default="auto",
                     help="auto: the learned cost model when one for this machine is shipped, else the case table")
-    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition, 1D Jacobi")
+    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition, 1D Jacobi, polynomial division")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
@@ -406,6 +443,7 @@ def main():
     transpose = None if args.no_grouped else transpose_section(tbl, pk, torch, inputs)
     madd = None if args.no_grouped else madd_section(tbl, pk, torch, inputs)
     jacobi = None if args.no_grouped else jacobi_section(tbl, pk, torch, inputs)
+    polydiv = None if args.no_grouped else polydiv_section(tbl, pk, torch)
     grouped = None
     if not args.no_grouped:
         grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
@@ -419,7 +457,7 @@ def main():
                       "parallelism": "none (1 GPU)"},
            "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
            "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "transpose": transpose,
-           "madd": madd, "jacobi": jacobi,
+           "madd": madd, "jacobi": jacobi, "polydiv": polydiv,
            "roofline": roofline,
            "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
     if not args.no_cpu_baseline:

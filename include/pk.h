@@ -84,7 +84,8 @@ typedef struct {
 #define PK_FAMILY_TRANSPOSE 2 /* matrix transposition (Section 5.2, Fig. 7), 4-byte elements */
 #define PK_FAMILY_MADD 3      /* matrix addition (Section 1, Fig. 1 and Fig. 2), f32 and i32 */
 #define PK_FAMILY_JACOBI 4    /* 1D Jacobi time step (Section 5, Fig. 6, Table 2), f32 and i32 */
-#define PK_NUM_FAMILIES 5
+#define PK_FAMILY_POLYDIV 5   /* polynomial division mod P (Section 5, Fig. 8, Table 4), u32 residues */
+#define PK_NUM_FAMILIES 6
 
 /* Strategy bits of the VALU family (a variant is the set of strategies applied):
  * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
@@ -118,7 +119,10 @@ typedef struct {
  * 1D Jacobi family: bx = work-items per workgroup (Fig. 6's B), s = points
  *   per work-item (s); by unused (0 or 1); strategy bits as the VALU family
  *   (PK_VALU_GRAN: s = 1, the second case; PK_VALU_NOLDS: no LDS caching,
- *   the third case). */
+ *   the third case).
+ * Polynomial-division family: bx = work-items per workgroup (Fig. 8's B),
+ *   s = coefficients per work-item; by unused (0 or 1); strategy bits as the
+ *   1D Jacobi family.  Its table is stored under PK_I32 (32-bit residues). */
 typedef struct {
     int32_t family;
     int32_t leaf;
@@ -305,6 +309,23 @@ int pk_select_madd(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, in
 int pk_jacobi1d(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, void *a, int64_t N,
                 int64_t steps, void *hip_stream);
 int pk_select_jacobi1d(const pk_table *tbl, pk_dtype dtype, int64_t N, int policy, pk_params *out);
+
+/* ------------------------------------------------------------------ polynomial division */
+/* Division modulo a prime (Section 5, Fig. 8), in place on device arrays:
+ * a holds the N coefficients of the dividend (a[i] multiplies x^i), b the M
+ * low coefficients of a monic divisor of degree M, b(x) = x^M + b[M-1]
+ * x^(M-1) + ... + b[0].  While the dividend's degree is at least M the
+ * leading coefficient q times x^(deg - M) b(x) is subtracted -- one kernel
+ * launch per step, N - M steps -- and a[M .. N-1] is cleared at the end, so a
+ * returns the remainder in a[0 .. M-1] (N <= M: nothing to do).  Every
+ * coefficient must be a residue in [0, P) (not checked: other values give an
+ * unspecified result); 2 <= P < 2^31 (PK_ERR_INVALID_ARG otherwise; P need
+ * not be prime, as b is monic).  N >= 0, M >= 1.  Asynchronous on
+ * hip_stream.  params_or_null: family PK_FAMILY_POLYDIV, resolved as in
+ * pk_matmul (NULL: the CASE choice).  Errors as pk_transpose. */
+int pk_polydiv(const pk_table *tbl, const pk_params *params_or_null, uint32_t *a, int64_t N, const uint32_t *b,
+               int64_t M, uint32_t P, void *hip_stream);
+int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_params *out);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */

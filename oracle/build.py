@@ -12,7 +12,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, "matmul.c"), os.path.join(HERE, "transpose.c"), os.path.join(HERE, "madd.c"),
-           os.path.join(HERE, "jacobi.c")]
+           os.path.join(HERE, "jacobi.c"), os.path.join(HERE, "polydiv.c")]
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liboracle.so")
 

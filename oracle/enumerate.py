@@ -28,6 +28,10 @@ enumeration over a grid of machines and the whole program-parameter domain:
   per workgroup) and s (points per work-item); programs as in the VALU
   family; the cached program holds the tile's s' * B inputs and one halo
   point on each side: 4 * (s' * B + 2) bytes; threads B.
+* Polynomial-division family (Section 5, Fig. 8): program parameters B and s
+  as the 1D Jacobi family; the cached program holds the tile's s' * B values
+  of a and of b and the leading coefficient: 4 * (2 * s' * B + 1) bytes;
+  threads B; 32-bit residues only (stored under the int32 dtype).
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -49,7 +53,7 @@ import numpy as np
 from . import comprehensive as co
 
 F32, I32, BF16 = 0, 1, 2
-VALU, MFMA, TRANSPOSE, MADD, JACOBI = 0, 1, 2, 3, 4
+VALU, MFMA, TRANSPOSE, MADD, JACOBI, POLYDIV = 0, 1, 2, 3, 4, 5
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 
@@ -91,6 +95,13 @@ def jacobi_lds(variant: int, b: int, s: int) -> int:
     return 4 * (outs * b + 2)
 
 
+def polydiv_lds(variant: int, b: int, s: int) -> int:
+    if variant & NOLDS:
+        return 0
+    outs = 1 if variant & GRAN else s
+    return 4 * (2 * outs * b + 1)
+
+
 def mfma_lds(dtype: int, variant: int, bm: int, bn: int, bk: int) -> int:
     stages = 1 if variant & SINGLE else 2
     if dtype == F32:
@@ -106,17 +117,17 @@ class InstanceData:
     def __init__(self, instances: List[dict]):
         self.by_key = {}
         for e in instances:
-            if e["family"] in (VALU, TRANSPOSE, MADD, JACOBI):
+            if e["family"] in (VALU, TRANSPOSE, MADD, JACOBI, POLYDIV):
                 key = (e["family"], e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
             else:
                 key = (MFMA, e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"], e["wm"], e["wn"])
             self.by_key[key] = e
 
     def regs(self, family: int, dtype: int, variant: int, point: Tuple[int, ...]):
-        if family == JACOBI:
+        if family in (JACOBI, POLYDIV):
             b, s = point
             outs = 1 if variant & GRAN else s
-            e = self.by_key.get((JACOBI, dtype, variant & NOLDS, b, 1, outs))
+            e = self.by_key.get((family, dtype, variant & NOLDS, b, 1, outs))
         elif family in (VALU, TRANSPOSE, MADD):
             bx, by, s = point
             kernel = variant & NOLDS
@@ -131,7 +142,7 @@ class InstanceData:
 
 
 def threads(family: int, point) -> int:
-    if family == JACOBI:
+    if family in (JACOBI, POLYDIV):
         return point[0]
     if family in (VALU, TRANSPOSE, MADD):
         return point[0] * point[1]
@@ -147,6 +158,8 @@ def lds(family: int, dtype: int, variant: int, point) -> int:
         return 0
     if family == JACOBI:
         return jacobi_lds(variant, *point)
+    if family == POLYDIV:
+        return polydiv_lds(variant, *point)
     return mfma_lds(dtype, variant, point[0], point[1], point[2])
 
 
@@ -181,7 +194,7 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
     pts = [tuple(p) for p in points]
     if family == MADD:
         return _madd_family(dtype, pts, inst)
-    if family == JACOBI:
+    if family in (JACOBI, POLYDIV):
         program = ["B", "s"]
         strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"})),
                       co.Strategy("nolds", False, frozenset({"r_Z", "r_V"}))]
@@ -191,6 +204,8 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
             a = set(applied)
             if "nolds" in a:
                 return co.Poly.const(0)
+            if family == POLYDIV:
+                return co.parse_poly("8*B + 4") if "gran" in a else co.parse_poly("8*s*B + 4")
             if "gran" in a:
                 return co.parse_poly("4*B + 8")
             return co.parse_poly("4*s*B + 8")

@@ -39,12 +39,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE,
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
 HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp",
                 "madd.cpp", "jacobi.cpp"]
-DEVICE_SOURCES = ["costmodel.hip"]
+DEVICE_SOURCES = ["costmodel.hip", "polydiv.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}
 DT_CTYPE = {F32: "float", I32: "int32_t"}
-FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA = 0, 1, 2, 3, 4
+FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA, FAM_PD = 0, 1, 2, 3, 4, 5
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
@@ -141,6 +141,17 @@ def instances():
                                  bm=0, bn=0, wm=0, wn=0, threads=b, lds=lds, tile_m=1, tile_n=s * b,
                                  args="pkk::JaArgs a")
                     out.append(("jacobi_%s" % DT_NAME[dt], name, body, entry))
+    # polynomial division steps: cached (LDS) and direct programs, 32-bit residues
+    for nolds in (False, True):
+        for b in JA_B:
+            for s in JA_S:
+                kind = "direct" if nolds else "tiled"
+                name = "pk_polydiv_%s_b%d_s%d" % (kind, b, s)
+                body = "pkk::polydiv_step_%s<%d, %d>(a);" % (kind, b, s)
+                entry = dict(family=FAM_PD, variant=VALU_NOLDS if nolds else 0, dtype=I32, bx=b, by=1, s=s, bk=0,
+                             bm=0, bn=0, wm=0, wn=0, threads=b, lds=0 if nolds else 4 * (2 * s * b + 1),
+                             tile_m=1, tile_n=s * b, args="pkk::PdArgs a")
+                out.append(("polydiv_steps", name, body, entry))
     # persistent grouped instances of the MFMA programs up to 128 x 128
     gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
     for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):
@@ -173,7 +184,7 @@ def generate():
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
                  "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"',
                  '#include "kernels/transpose.hpp"', '#include "kernels/madd.hpp"',
-                 '#include "kernels/jacobi.hpp"', ""]
+                 '#include "kernels/jacobi.hpp"', '#include "kernels/polydiv.hpp"', ""]
         for name, body, entry in items:
             arg = entry.get("args", "pkk::MmArgs a")
             lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'

@@ -71,12 +71,20 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
     return PK_OK;
 }
 
-// blocks of an instance resident on one compute unit
+// Workgroups of an instance resident on one compute unit: wave slots
+// (max_threads_cu / wave, a workgroup holding whole wavefronts), LDS and
+// registers, and the runtime's workgroup limit -- unless that limit is no
+// more than max_threads_cu / max_threads_block, a figure that only describes
+// full-size workgroups (one HIP runtime reports 2 for gfx950, another 32).
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e) {
     const KernelResources *r = resources_of(e.name);
-    int64_t b = m.max_blocks_cu > 0 ? m.max_blocks_cu : 32;
+    const int64_t wave = m.wave > 0 ? m.wave : 64;
+    const int64_t waves = (e.threads + wave - 1) / wave;
+    int64_t b = m.max_threads_cu > 0 ? std::max<int64_t>(1, m.max_threads_cu / wave) / waves : 32;
+    const bool derived = m.max_threads_block > 0 && m.max_threads_cu > 0 &&
+                         (int64_t)m.max_blocks_cu * m.max_threads_block <= m.max_threads_cu;
+    if (m.max_blocks_cu > 0 && !derived) b = std::min<int64_t>(b, m.max_blocks_cu);
     if (e.lds_bytes > 0) b = std::min<int64_t>(b, m.lds_cu / e.lds_bytes);
-    if (m.max_threads_cu > 0) b = std::min<int64_t>(b, m.max_threads_cu / e.threads);
     if (r) {
         int64_t rb = regs_per_block(*r, e.threads, m.wave > 0 ? m.wave : 64);
         if (rb > 0) b = std::min<int64_t>(b, m.regs_cu / rb);
@@ -205,8 +213,9 @@ int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table
                 pk_table::Part part;
                 part.family = family;
                 part.dtype = dtype;
-                const bool ok = family == PK_FAMILY_MFMA ? (dtype == PK_F32 || dtype == PK_BF16)
-                                                         : (dtype == PK_F32 || dtype == PK_I32);
+                const bool ok = family == PK_FAMILY_MFMA      ? (dtype == PK_F32 || dtype == PK_BF16)
+                                : family == PK_FAMILY_POLYDIV ? dtype == PK_I32
+                                                              : (dtype == PK_F32 || dtype == PK_I32);
                 part.supported = ok;
                 if (ok) {
                     part.fam = matmul_family(family, dtype);

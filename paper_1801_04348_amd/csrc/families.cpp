@@ -39,6 +39,11 @@
 // 4 * (s * B + 2) -- the tile's inputs with one halo point on each side (the
 // paper's program caches inputs and outputs, 2 s B + 2 words).
 //
+// Polynomial-division family (Section 5, Fig. 8): program parameters B and
+// s as the 1D Jacobi family, same strategies.  LDS bytes of the cached
+// program: 4 * (2 * s * B + 1) -- the tile's a and b values and the leading
+// coefficient (the paper's program, 2 s B + 2 words).
+//
 // MFMA family, program parameters bm, bn (output tile), bk (K tile), wm, wn
 // (wavefront grid).  Strategy:
 //   single (source; sigma = {r_Z, r_V}) one LDS stage instead of two (also no
@@ -166,7 +171,9 @@ Family matmul_family(int family, int dtype) {
         };
         return f;
     }
-    if (family == PK_FAMILY_JACOBI) {
+    if (family == PK_FAMILY_JACOBI || family == PK_FAMILY_POLYDIV) {
+        const bool pd = family == PK_FAMILY_POLYDIV;
+        if (pd && dtype != PK_I32) throw std::runtime_error("polynomial division: 32-bit residues (i32) only");
         if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("1D Jacobi: f32 and i32 only");
         const int b = add_sym(f, "B", SYM_PROGRAM), s = add_sym(f, "s", SYM_PROGRAM);
         const int rho_t = add_sym(f, "rho_tiled", SYM_TABLE), rho_t1 = add_sym(f, "rho_tiled_s1", SYM_TABLE),
@@ -174,8 +181,8 @@ Family matmul_family(int family, int dtype) {
         f.point_syms = {b, s};
         for (int x : kJaB)
             for (int z : kJaS) f.points.push_back({x, z});
-        const Poly lds_full = P(4) * (S(s) * S(b) + P(2));
-        const Poly lds_g1 = P(4) * (S(b) + P(2));
+        const Poly lds_full = pd ? P(8) * S(s) * S(b) + P(4) : P(4) * (S(s) * S(b) + P(2));
+        const Poly lds_g1 = pd ? P(8) * S(b) + P(4) : P(4) * (S(b) + P(2));
         CounterDef rz{"r_Z", false, m.Z, nullptr};
         rz.value = [=](uint32_t ap) {
             if (ap & PK_VALU_NOLDS) return P(0);
@@ -195,7 +202,7 @@ Family matmul_family(int family, int dtype) {
             int variant = 0;
             if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
             if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
-            return table_regs(PK_FAMILY_JACOBI, variant, dtype, pt, 64);
+            return table_regs(family, variant, dtype, pt, 64);
         };
         return f;
     }
@@ -286,7 +293,7 @@ Family matmul_family(int family, int dtype) {
 }
 
 bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
-    if (family == PK_FAMILY_JACOBI) {
+    if (family == PK_FAMILY_JACOBI || family == PK_FAMILY_POLYDIV) {
         if (p.by != 0 && p.by != 1) return false;
         *pt = {p.bx, p.s};
         return true;
@@ -310,7 +317,7 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
     p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
-    if (family == PK_FAMILY_JACOBI) {
+    if (family == PK_FAMILY_JACOBI || family == PK_FAMILY_POLYDIV) {
         p->bx = (int32_t)pt[0];
         p->by = 1;
         p->s = (int32_t)pt[1];
@@ -354,7 +361,7 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     int kind = 0;
     std::vector<int64_t> q = pt;
     if (family == PK_FAMILY_TRANSPOSE) dtype = PK_F32;  // a bit copy: one instance serves every 4-byte type
-    if (family == PK_FAMILY_JACOBI) {
+    if (family == PK_FAMILY_JACOBI || family == PK_FAMILY_POLYDIV) {
         const int64_t s = (variant & PK_VALU_GRAN) ? 1 : pt[1];
         for (const auto &e : registry())
             if (e.family == family && e.dtype == dtype && e.variant == (variant & PK_VALU_NOLDS) && e.bx == pt[0] &&

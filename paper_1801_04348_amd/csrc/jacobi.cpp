@@ -35,14 +35,9 @@ int run_steps(const pk_machine &m, const KernelEntry &e, void *a, int64_t N, int
 
 double estimate_ja(const pk_machine &m, const KernelEntry &e, int64_t N) {
     const int64_t n = std::max<int64_t>(N - 2, 0);
-    const double bytes = 8.0 * (double)n;
     const int64_t tiles = (n + e.tile_n - 1) / e.tile_n;
-    const int64_t slots = (int64_t)m.cu_count * blocks_per_cu(m, e);
-    const int64_t rounds = std::max<int64_t>(1, (tiles + slots - 1) / slots);
-    const double fill = (double)std::max<int64_t>(tiles, 1) / ((double)rounds * slots);
-    // more outputs per work-item keep more loads in flight
-    const double eff = ((e.variant & PK_VALU_NOLDS) ? 0.55 : 0.6) + 0.3 * std::min(1.0, e.s / 4.0);
-    return bytes / (8e12 * eff * std::min(1.0, fill + 0.25)) + 2e-6;
+    return streaming_seconds(m, e, 8.0 * (double)n, tiles, 4.0 * (double)(e.tile_n + 2),
+                             4.0 * std::min<int64_t>(e.threads, 64));
 }
 
 }  // namespace

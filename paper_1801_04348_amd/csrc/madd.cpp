@@ -26,14 +26,11 @@ int launch_ma(const pk_machine &m, const KernelEntry &e, const pkk::MaArgs &args
 }
 
 double estimate_ma(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N) {
-    const double bytes = 12.0 * (double)M * (double)N;
     const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
-    const int64_t slots = (int64_t)m.cu_count * blocks_per_cu(m, e);
-    const int64_t rounds = std::max<int64_t>(1, (tiles + slots - 1) / slots);
-    const double fill = (double)tiles / ((double)rounds * slots);
-    // more outstanding loads per work-item hide more latency
-    const double eff = 0.6 + 0.3 * std::min(1.0, e.s / 4.0);
-    return bytes / (8e12 * eff * std::min(1.0, fill + 0.25)) + 4e-6;
+    // per tile, every work-item issues its S loads of A and of B before adding
+    const double inflight = 8.0 * e.tile_m * e.tile_n;
+    return streaming_seconds(m, e, 12.0 * (double)M * (double)N, tiles, inflight,
+                             4.0 * std::min<int64_t>(e.bx, 64));
 }
 
 }  // namespace

@@ -57,6 +57,23 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
 }
 }  // namespace
 
+double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes, int64_t tiles,
+                         double inflight_bytes_per_tile, double segment_bytes) {
+    const int64_t ncu = std::max<int32_t>(m.cu_count, 1);
+    const int64_t bpc = blocks_per_cu(m, e);
+    tiles = std::max<int64_t>(tiles, 1);
+    const int64_t per_cu = (tiles + ncu - 1) / ncu;  // tiles of the busiest compute unit
+    const int64_t active = std::min(ncu, tiles);
+    const double imbalance = (double)(per_cu * ncu) / (double)tiles;
+    const double resident = (double)std::min(bpc, per_cu);
+    const double inflight = std::min(1.0, resident * inflight_bytes_per_tile / 65536.0);
+    const double seg = std::min(1.0, segment_bytes / 128.0);
+    // one compute unit alone draws about 64 GB/s; all of them, 8 TB/s
+    const double bw = std::min(8e12, 64e9 * (double)active) * 0.85 * std::max(inflight * seg, 1e-3);
+    const double rounds = (double)((per_cu + bpc - 1) / bpc);
+    return bytes * (tiles >= ncu ? imbalance : 1.0) / bw + 0.5e-6 * rounds + 3e-6;
+}
+
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K) {
     const double clock = (m.clock_khz > 0 ? m.clock_khz : 2400000) * 1e3;
     const int64_t tm = (M + e.tile_m - 1) / e.tile_m, tn = (N + e.tile_n - 1) / e.tile_n;

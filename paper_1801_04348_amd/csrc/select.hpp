@@ -27,6 +27,15 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
 // Analytic time of one launch (the CASE score).
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K);
 
+// Analytic time of one launch of a streaming (HBM-bound) kernel moving
+// `bytes`: compulsory bytes over 8 TB/s, scaled by the share one launch can
+// sustain -- the filled share of the last round of tiles, the bytes a compute
+// unit keeps in flight (about 64 KiB per compute unit covers HBM latency at
+// full bandwidth), and the narrowest contiguous segment a wavefront touches
+// (below 128 bytes a cache line is partly wasted) -- plus launch latency.
+double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes, int64_t tiles,
+                         double inflight_bytes_per_tile, double segment_bytes);
+
 int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, int policy, bool cache,
                   pk_params *out, const void *A = nullptr, int64_t lda = 0, const void *B = nullptr,
                   int64_t ldb = 0);

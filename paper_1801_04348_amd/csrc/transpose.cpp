@@ -28,16 +28,13 @@ int launch_tr(const pk_machine &m, const KernelEntry &e, const pkk::TrArgs &args
 }
 
 double estimate_tr(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N) {
-    const double bytes = 8.0 * (double)M * (double)N;
     const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
-    const int64_t slots = (int64_t)m.cu_count * blocks_per_cu(m, e);
-    const int64_t rounds = std::max<int64_t>(1, (tiles + slots - 1) / slots);
-    const double fill = (double)tiles / ((double)rounds * slots);
-    // share of HBM bandwidth a program sustains: both sides coalesced through
-    // LDS, or strided writes without it; small tiles pay per-tile overhead
-    double eff = (e.variant & PK_VALU_NOLDS) ? 0.35 : 0.85;
-    eff *= std::min(1.0, (double)(e.tile_m * e.tile_n) / 2048.0 + 0.5);
-    return bytes / (8e12 * eff * std::min(1.0, fill + 0.25)) + 4e-6;
+    // reads run along rows of A (bx elements); the cached program writes
+    // along rows of C (by * s elements), the direct one 4-byte strided
+    const double rd = 4.0 * std::min<int64_t>(e.bx, 64);
+    const double wr = (e.variant & PK_VALU_NOLDS) ? 4.0 : 4.0 * std::min<int64_t>(e.tile_m, 64);
+    return streaming_seconds(m, e, 8.0 * (double)M * (double)N, tiles, 4.0 * e.tile_m * e.tile_n,
+                             std::min(rd, wr));
 }
 
 struct TrCand {

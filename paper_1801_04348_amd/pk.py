@@ -34,7 +34,8 @@ PK_ERR_BUFFER_TOO_SMALL = -7
 PK_ERR_PARSE = -8
 
 PK_F32, PK_I32, PK_BF16 = 0, 1, 2
-PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_JACOBI = 0, 1, 2, 3, 4
+PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_JACOBI, PK_FAMILY_POLYDIV = (
+    0, 1, 2, 3, 4, 5)
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
@@ -133,6 +134,10 @@ def lib():
         L.pk_jacobi1d.restype = i32
         L.pk_select_jacobi1d.argtypes = [vp, i32, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_jacobi1d.restype = i32
+        L.pk_polydiv.argtypes = [vp, ctypes.POINTER(pk_params), vp, i64, vp, i64, ctypes.c_uint32, vp]
+        L.pk_polydiv.restype = i32
+        L.pk_select_polydiv.argtypes = [vp, i64, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_polydiv.restype = i32
         L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
         L.pk_kernel_name.restype = ctypes.c_char_p
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -322,6 +327,23 @@ def pk_jacobi1d(tbl: Table, p, dtype, a, steps: int, stream=None):
         raise ValueError("a must be a contiguous 1-D array of even length")
     _check(lib().pk_jacobi1d(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype),
                              ctypes.c_void_p(a.data_ptr()), a.numel() // 2, steps, _stream(stream)))
+
+
+def pk_select_polydiv(tbl: Table, N: int, M: int, policy: int = PK_POLICY_CASE) -> pk_params:
+    out = pk_params()
+    _check(lib().pk_select_polydiv(tbl.handle, N, M, policy, ctypes.byref(out)))
+    return out
+
+
+def pk_polydiv(tbl: Table, p, a, b, P: int, stream=None):
+    """Divides, in place on the device, the polynomial a (N int32 words holding
+    residues in [0, P)) by the monic polynomial x^M + b (b: its M low
+    coefficients); a returns the remainder in a[:M], zeros above."""
+    for t in (a, b):
+        if t.dim() != 1 or not t.is_contiguous() or t.element_size() != 4:
+            raise ValueError("a and b must be contiguous 1-D arrays of 32-bit words")
+    _check(lib().pk_polydiv(tbl.handle, ctypes.byref(p) if p is not None else None, ctypes.c_void_p(a.data_ptr()),
+                            a.numel(), ctypes.c_void_p(b.data_ptr()), b.numel(), P, _stream(stream)))
 
 
 def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:

@@ -127,6 +127,8 @@ def test_lds_counter_equals_compiled_lds(gfx_desc):
             assert e["lds_bytes"] == 0
         elif e["family"] == en.JACOBI:
             assert e["lds_bytes"] == en.jacobi_lds(e["variant"], e["bx"], e["s"])
+        elif e["family"] == en.POLYDIV:
+            assert e["lds_bytes"] == en.polydiv_lds(e["variant"], e["bx"], e["s"])
         else:
             assert e["lds_bytes"] == en.mfma_lds(e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"])
         assert e["scratch"] == 0, e["name"]   # no register spills in any instance
@@ -201,7 +203,8 @@ def test_optimality_definition_3_iv(gfx_desc):
              1: {"r_Z": {"single"}, "r_V": {"single"}, "r_T": set()},
              2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
              3: {"r_V": {"gran"}, "r_T": set()},
-             4: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
+             4: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
+             5: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
     for part in gfx_desc["parts"]:
         for counter, strategies in sigma[part["family"]].items():
             assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
@@ -338,3 +341,22 @@ def test_jacobi_table_follows_fig6_cases():
         pk.pk_select_jacobi1d(t, "i32", 1)
     with pytest.raises(pk.PkError):
         pk.pk_case_table_lookup(t, "i32", pk.params(family=pk.PK_FAMILY_JACOBI, bx=256, by=2, s=1))
+
+
+def test_polydiv_table_follows_fig8_cases():
+    # Section 5, Fig. 8: the cached program while its LDS fits, granularity 1
+    # while that fits, then no LDS; LDS bytes 4*(2*s*B + 1) and 4*(2*B + 1)
+    V, T = 131072, 1024
+    p = pk.params(family=pk.PK_FAMILY_POLYDIV, bx=128, s=4)
+    for Z, want in ((65536, 0), (4100, 0), (4099, pk.PK_VALU_GRAN), (1028, pk.PK_VALU_GRAN),
+                    (1027, pk.PK_VALU_GRAN | pk.PK_VALU_NOLDS)):
+        t = pk.pk_case_table_build(0, machines.grid_machine(Z, V, T))
+        leaf, var = pk.pk_case_table_lookup(t, "i32", p)
+        assert var == want, (Z, var)
+        with pytest.raises(pk.PkError):
+            pk.pk_case_table_lookup(t, "f32", p)
+    t = pk.pk_case_table_build(0, machines.gfx950())
+    q = pk.pk_select_polydiv(t, 2 ** 15 + 100, 2 ** 15)
+    assert q.family == pk.PK_FAMILY_POLYDIV
+    with pytest.raises(pk.PkError):
+        pk.pk_select_polydiv(t, 10, 0)
