@@ -122,7 +122,15 @@ typedef struct {
  *   the third case).
  * Polynomial-division family: bx = work-items per workgroup (Fig. 8's B),
  *   s = coefficients per work-item; by unused (0 or 1); strategy bits as the
- *   1D Jacobi family.  Its table is stored under PK_I32 (32-bit residues). */
+ *   1D Jacobi family.  Its table is stored under PK_I32 (32-bit residues).
+ *   variant PK_POLYDIV_FUSED (with leaf = -1) selects this library's
+ *   one-launch program instead of the paper's one launch per step: the
+ *   quotient first (a short recurrence in one wavefront of every
+ *   workgroup), then every remainder coefficient in parallel; it needs
+ *   N - M <= 1024 and bx >= 64 and is not part of the case table (its
+ *   resources are checked against the machine when it is chosen). */
+#define PK_POLYDIV_FUSED 4
+#define PK_POLYDIV_WIDE 8 /* internal: the instance holding up to 1024 quotient coefficients */
 typedef struct {
     int32_t family;
     int32_t leaf;

@@ -95,7 +95,12 @@ def jacobi_lds(variant: int, b: int, s: int) -> int:
     return 4 * (outs * b + 2)
 
 
+FUSED = 4                   # polynomial division: the one-launch program
+
+
 def polydiv_lds(variant: int, b: int, s: int) -> int:
+    if variant & FUSED:         # quotient, top of b, b window of a tile
+        return 4 * (3 * 1024 + s * b)
     if variant & NOLDS:
         return 0
     outs = 1 if variant & GRAN else s

@@ -152,6 +152,16 @@ def instances():
                              bm=0, bn=0, wm=0, wn=0, threads=b, lds=0 if nolds else 4 * (2 * s * b + 1),
                              tile_m=1, tile_n=s * b, args="pkk::PdArgs a")
                 out.append(("polydiv_steps", name, body, entry))
+    # one-launch polynomial division (quotient recurrence, then the remainder)
+    for b in (64, 128, 256, 512, 1024):
+        for s in JA_S:
+            for r in (2, 16):
+                name = "pk_polydiv_fused_b%d_s%d_k%d" % (b, s, 64 * r)
+                body = "pkk::polydiv_fused<%d, %d, %d>(a);" % (b, s, r)
+                entry = dict(family=FAM_PD, variant=4 | (8 if r == 16 else 0), dtype=I32, bx=b, by=1, s=s, bk=0,
+                             bm=0, bn=0, wm=0, wn=0, threads=b, lds=4 * (3 * 1024 + s * b), tile_m=1, tile_n=s * b,
+                             args="pkk::PdArgs a")
+                out.append(("polydiv_fused", name, body, entry))
     # persistent grouped instances of the MFMA programs up to 128 x 128
     gfn = {F32: "grouped_f32", BF16: "grouped_bf16"}
     for dt, cfgs in ((F32, MFMA_F32), (BF16, MFMA_BF16)):

@@ -360,6 +360,11 @@ const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dty
     }
     pk_params q;
     const KernelEntry *e = nullptr;
+    if (p->family == PK_FAMILY_POLYDIV && p->variant >= 0 && (p->variant & PK_POLYDIV_FUSED)) {
+        e = find_polydiv_fused(p->variant, p->bx, p->s);
+        if (!e) fail(PK_ERR_NOT_INSTANTIATED, "no one-launch division instance for these parameters");
+        return e ? e->name : nullptr;
+    }
     if (resolve(tbl, p, (int)dtype, &q, &e) != PK_OK) return nullptr;
     return e->name;
 }
@@ -370,8 +375,13 @@ int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int
     if (!tbl || !p) return fail(PK_ERR_INVALID_ARG, "null argument");
     pk_params q;
     const KernelEntry *e = nullptr;
-    int rc = resolve(tbl, p, (int)dtype, &q, &e);
-    if (rc != PK_OK) return rc;
+    if (p->family == PK_FAMILY_POLYDIV && p->variant >= 0 && (p->variant & PK_POLYDIV_FUSED)) {
+        e = find_polydiv_fused(p->variant, p->bx, p->s);
+        if (!e) return fail(PK_ERR_NOT_INSTANTIATED, "no one-launch division instance for these parameters");
+    } else {
+        int rc = resolve(tbl, p, (int)dtype, &q, &e);
+        if (rc != PK_OK) return rc;
+    }
     if (grid) *grid = grid_of(tbl->machine, *e, M, N);
     if (block) *block = e->threads;
     if (lds_bytes) *lds_bytes = e->lds_bytes;

@@ -386,4 +386,11 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
     return nullptr;
 }
 
+const KernelEntry *find_polydiv_fused(int variant, int64_t bx, int64_t s) {
+    const int v = variant & (PK_POLYDIV_FUSED | PK_POLYDIV_WIDE);
+    for (const auto &e : registry())
+        if (e.family == PK_FAMILY_POLYDIV && e.variant == v && e.bx == bx && e.s == s) return &e;
+    return nullptr;
+}
+
 }  // namespace pk

@@ -93,3 +93,89 @@ __device__ __forceinline__ void polydiv_step_direct(const PdArgs &g) {
 }
 
 }  // namespace pkk
+
+namespace pkk {
+
+// The whole division in one launch (a program of this library, not one of
+// the paper's): the K = n - M quotient coefficients first, then every
+// remainder coefficient independently.  With top[j] the dividend coefficient
+// at index n-1-j, step j of the division subtracts q_j b[M-d] from top[j+d]
+// (1 <= d <= M), so q_k is top[k] after the steps before it -- a short
+// sequential recurrence -- and the remainder is
+//     r[x] = a[x] - sum_{0 <= j < K} q_j b[x - (K-1) + j]   (terms with a
+//     b index below 0 vanish),
+// K products per coefficient, no dependence between coefficients.
+// Phase 1 runs in the first wavefront of every workgroup (redundantly, so no
+// grid-wide synchronisation is needed): lane l keeps top[l + 64 r], r < R, in
+// registers, the coefficient q_k is broadcast from its owner with a lane
+// read, and b[M-1-i] is staged in LDS.  Phase 2: each workgroup stages the b
+// window of its tile of S * B remainder coefficients and reads the quotient
+// from LDS.  Needs K <= 64 * R <= 1024 and B >= 64.  LDS bytes:
+// 4 * (2 * 1024 + S * B + 1024).  a[M .. n-1] are left for the host to clear.
+constexpr int kPdMaxK = 1024;
+
+__device__ __forceinline__ uint32_t barrett(uint64_t t, uint32_t P, uint64_t mu) {
+    const uint64_t q = __umul64hi(t, mu);
+    uint64_t r = t - q * P;
+    if (r >= P) r -= P;
+    return (uint32_t)r;
+}
+
+template <int B, int S, int R>
+__device__ __forceinline__ void polydiv_fused(const PdArgs &g) {
+    static_assert(B % 64 == 0 && R * 64 <= kPdMaxK, "fused division: whole wavefronts, K <= 1024");
+    constexpr int TW = S * B;
+    __shared__ uint32_t qs[kPdMaxK];
+    __shared__ uint32_t bt[kPdMaxK];          // bt[i] = b[M-1-i]
+    __shared__ uint32_t bw[TW + kPdMaxK];     // b window of a remainder tile
+    const int M = g.M, n = g.n, K = n - M;
+    const uint32_t P = g.P;
+    const uint64_t mu = g.mu;
+    const int t = threadIdx.x, lane = t & 63;
+    const int nb = min(K, M);
+    for (int i = t; i < nb; i += B) bt[i] = g.b[M - 1 - i];
+    __syncthreads();
+    if (t < 64) {
+        uint32_t top[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = lane + 64 * r;
+            top[r] = j < K ? g.a[n - 1 - j] : 0u;
+        }
+        for (int k = 0; k < K; ++k) {
+            uint32_t mine = top[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                if (r == (k >> 6)) mine = top[r];
+            const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)mine, k & 63);
+            if (lane == 0) qs[k] = q;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int d = lane + 64 * r - k;  // top[k + d] receives q b[M - d]
+                if (d >= 1 && d <= nb && k + d < K) top[r] = submod(top[r], barrett((uint64_t)q * bt[d - 1], P, mu), P);
+            }
+        }
+    }
+    __syncthreads();
+    const int tiles = (M + TW - 1) / TW;
+    for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int x0 = tile * TW;
+        for (int i = t; i < TW + K - 1; i += B) {
+            const int p = x0 - (K - 1) + i;
+            bw[i] = (p >= 0 && p < M) ? g.b[p] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int xl = t + s * B, x = x0 + xl;
+            if (x < M) {
+                uint64_t acc = 0;
+                for (int j = 0; j < K; ++j) acc += barrett((uint64_t)qs[j] * bw[xl + j], P, mu);
+                g.a[x] = submod(g.a[x], barrett(acc, P, mu), P);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace pkk

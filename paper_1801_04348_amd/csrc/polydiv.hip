@@ -44,6 +44,55 @@ int run_division(const pk_machine &m, const KernelEntry &e, uint32_t *a, int64_t
     return PK_OK;
 }
 
+// The one-launch program (kernels/polydiv.hpp, polydiv_fused) for a B x S
+// point and K = N - M quotient coefficients: the instance whose register
+// slots hold K, if it exists and fits the machine.
+const KernelEntry *find_fused(const pk_machine &m, int64_t B, int64_t S, int64_t K) {
+    if (K < 1 || K > pkk::kPdMaxK) return nullptr;
+    const int variant = PK_POLYDIV_FUSED | (K > 128 ? PK_POLYDIV_WIDE : 0);
+    for (const auto &e : registry()) {
+        if (e.family != PK_FAMILY_POLYDIV || e.variant != variant || e.bx != B || e.s != S) continue;
+        if (e.lds_bytes > m.lds_block || e.threads > m.max_threads_block) return nullptr;
+        const KernelResources *r = resources_of(e.name);
+        if (!r || regs_per_block(*r, e.threads, m.wave > 0 ? m.wave : 64) > m.regs_block) return nullptr;
+        return &e;
+    }
+    return nullptr;
+}
+
+int run_fused(const pk_machine &m, const KernelEntry &e, uint32_t *a, int64_t N, const uint32_t *b, int64_t M,
+              uint32_t P, hipStream_t stream) {
+    if (N <= M) return PK_OK;
+    const int64_t grid = grid_of(m, e, 1, M);
+    pkk::PdArgs g{a, b, (int32_t)M, (int32_t)N, P, barrett_mu(P)};
+    void *kargs[] = {&g};
+    hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);
+    if (err != hipSuccess)
+        return fail(PK_ERR_HIP, std::string("hipLaunchKernel(") + e.name + "): " + hipGetErrorString(err));
+    const int64_t span = N - M;
+    const unsigned cg = (unsigned)std::min<int64_t>((span + 255) / 256, 1024);
+    hipLaunchKernelGGL(pd_clear, dim3(cg), dim3(256), 0, stream, a, M, N);
+    err = hipGetLastError();
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("pd_clear: ") + hipGetErrorString(err));
+    return PK_OK;
+}
+
+double estimate_fused(const pk_machine &m, const KernelEntry &e, int64_t N, int64_t M) {
+    const double K = (double)(N - M);
+    const double clock = m.clock_khz > 0 ? m.clock_khz * 1e3 : 2.4e9;
+    // phase 1: a dependent chain of K steps, each a lane read, a product
+    // reduction and the register-slot updates of one wavefront
+    const double slots = (e.variant & PK_POLYDIV_WIDE) ? 16.0 : 2.0;
+    const double phase1 = K * (160.0 + 60.0 * slots) / clock;
+    // phase 2: K reduced products per remainder coefficient, about 16 VALU
+    // instructions each, over the resident lanes
+    const int64_t tiles = (M + e.tile_n - 1) / e.tile_n;
+    const double lanes = (double)std::min<int64_t>(tiles, (int64_t)m.cu_count * blocks_per_cu(m, e)) * e.threads;
+    const double lane_rate = std::min(lanes, (double)m.cu_count * 64.0 * 4.0) * clock / 4.0;
+    const double phase2 = (double)M * K * 16.0 / std::max(lane_rate, 1.0);
+    return phase1 + phase2 + 6e-6;
+}
+
 double estimate_pd(const pk_machine &m, const KernelEntry &e, int64_t N, int64_t M) {
     if (N <= M) return 0.0;
     const int64_t tiles = (M + e.tile_n - 1) / e.tile_n;
@@ -88,6 +137,11 @@ int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_
             const KernelEntry *e = find_instance(PK_FAMILY_POLYDIV, variant, PK_I32, part->fam.points[i]);
             if (e) c.push_back(C{(int)i, leaf, variant, e, estimate_pd(tbl->machine, *e, N, M)});
         }
+        for (size_t i = 0; i < part->fam.points.size(); ++i) {
+            const auto &pt = part->fam.points[i];
+            const KernelEntry *e = find_fused(tbl->machine, pt[0], pt[1], N - M);
+            if (e) c.push_back(C{(int)i, -1, PK_POLYDIV_FUSED, e, estimate_fused(tbl->machine, *e, N, M)});
+        }
         if (c.empty()) return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no polynomial-division leaf holds");
         auto key = std::make_tuple(400, N, M, (int64_t)0, policy);
         {
@@ -114,9 +168,13 @@ int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_
             hipEventCreate(&e1);
             double best = std::numeric_limits<double>::infinity();
             for (size_t i = 0; i < c.size(); ++i) {
-                if (run_division(tbl->machine, *c[i].e, a, N, b, M, 65521u, s) != PK_OK) continue;
+                auto go = [&]() {
+                    return c[i].leaf < 0 ? run_fused(tbl->machine, *c[i].e, a, N, b, M, 65521u, s)
+                                         : run_division(tbl->machine, *c[i].e, a, N, b, M, 65521u, s);
+                };
+                if (go() != PK_OK) continue;
                 hipEventRecord(e0, s);
-                run_division(tbl->machine, *c[i].e, a, N, b, M, 65521u, s);
+                go();
                 hipEventRecord(e1, s);
                 hipEventSynchronize(e1);
                 float ms = 0.f;
@@ -138,7 +196,7 @@ int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_
         }
         point_params(PK_FAMILY_POLYDIV, part->fam.points[c[pick].point], out);
         out->leaf = c[pick].leaf;
-        out->variant = c[pick].variant;
+        out->variant = c[pick].leaf < 0 ? c[pick].e->variant : c[pick].variant;
         std::lock_guard<std::mutex> g(tbl->cache_mu);
         tbl->cache[key] = *out;
         return PK_OK;
@@ -161,6 +219,12 @@ int pk_polydiv(const pk_table *tbl, const pk_params *params_or_null, uint32_t *a
         params_or_null = &sel;
     }
     if (params_or_null->family != PK_FAMILY_POLYDIV) return fail(PK_ERR_INVALID_ARG, "parameters of another family");
+    if (params_or_null->variant >= 0 && (params_or_null->variant & PK_POLYDIV_FUSED)) {
+        if (N - M > pkk::kPdMaxK) return fail(PK_ERR_INVALID_ARG, "one-launch division needs N - M <= 1024");
+        const KernelEntry *e = find_fused(tbl->machine, params_or_null->bx, params_or_null->s, N - M);
+        if (!e) return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no one-launch division instance fits for these parameters");
+        return run_fused(tbl->machine, *e, a, N, b, M, P, (hipStream_t)hip_stream);
+    }
     pk_params q;
     const KernelEntry *e = nullptr;
     rc = resolve(tbl, params_or_null, PK_I32, &q, &e);

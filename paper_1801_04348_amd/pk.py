@@ -37,6 +37,7 @@ PK_F32, PK_I32, PK_BF16 = 0, 1, 2
 PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_JACOBI, PK_FAMILY_POLYDIV = (
     0, 1, 2, 3, 4, 5)
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
+PK_POLYDIV_FUSED, PK_POLYDIV_WIDE = 4, 8
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
 

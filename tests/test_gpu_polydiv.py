@@ -111,3 +111,37 @@ def test_large_divisor(table):
     N = M + 40
     a, b = residues(N, P31, 77), residues(M, P31, 78)
     assert np.array_equal(run(table, None, a, b, P31), oracle(a, b, P31))
+
+
+def fused(b, s):
+    return pk.params(family=pk.PK_FAMILY_POLYDIV, leaf=-1, variant=pk.PK_POLYDIV_FUSED, bx=b, s=s)
+
+
+@pytest.mark.parametrize("b", [64, 128, 256, 512, 1024])
+def test_one_launch_program(table, ragged, b):
+    # quotient recurrence then the remainder in parallel: every point, K <= 128
+    for a, bb, P, ref in ragged:
+        for s in (1, 2, 4, 8):
+            say("polydiv fused P=%d B=%d s=%d K=%d" % (P, b, s, a.numel() - bb.numel()))
+            assert np.array_equal(run(table, fused(b, s), a, bb, P), ref), (b, s)
+
+
+@pytest.mark.parametrize("N,M", [(3001 + 700, 3001), (1024 + 2000, 2000), (300, 5), (1030, 6), (129, 1), (5000, 4999)])
+def test_one_launch_quotient_lengths(table, N, M):
+    # K = N - M across the register-slot boundary (128) up to 1024, and K > M
+    a, b = residues(N, P31, N), residues(M, P31, N + 1)
+    ref = oracle(a, b, P31)
+    for bx, s in ((64, 1), (256, 4), (1024, 2)):
+        say("polydiv fused N=%d M=%d B=%d s=%d" % (N, M, bx, s))
+        assert np.array_equal(run(table, fused(bx, s), a, b, P31), ref), (bx, s)
+
+
+def test_one_launch_refusals(table):
+    a, b = residues(3000, 7, 1), residues(1000, 7, 2)   # K = 2000 > 1024
+    with pytest.raises(pk.PkError):
+        run(table, fused(256, 1), a, b, 7)
+    a, b = residues(300, 7, 1), residues(200, 7, 2)
+    with pytest.raises(pk.PkError):                      # workgroups of less than a wavefront
+        run(table, fused(32, 1), a, b, 7)
+    p = pk.pk_select_polydiv(table, 2 ** 15 + 100, 2 ** 15)
+    say("polydiv M=2^15 case pick", p, pk.pk_kernel_name(table, p, "i32"))

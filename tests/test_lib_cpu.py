@@ -360,3 +360,17 @@ def test_polydiv_table_follows_fig8_cases():
     assert q.family == pk.PK_FAMILY_POLYDIV
     with pytest.raises(pk.PkError):
         pk.pk_select_polydiv(t, 10, 0)
+
+
+def test_polydiv_one_launch_program_selection():
+    t = pk.pk_case_table_build(0, machines.gfx950())
+    p = pk.pk_select_polydiv(t, 2 ** 15 + 100, 2 ** 15)
+    assert p.variant & pk.PK_POLYDIV_FUSED and p.leaf == -1
+    assert pk.pk_kernel_name(t, p, "i32").startswith("pk_polydiv_fused_")
+    # beyond 1024 quotient coefficients only the per-step programs remain
+    p = pk.pk_select_polydiv(t, 5000, 1000)
+    assert not (p.variant & pk.PK_POLYDIV_FUSED) and p.leaf >= 0
+    # a machine whose LDS cannot hold the quotient falls back to the steps
+    small = pk.pk_case_table_build(0, machines.grid_machine(4096, 131072, 1024))
+    p = pk.pk_select_polydiv(small, 2 ** 15 + 100, 2 ** 15)
+    assert not (p.variant & pk.PK_POLYDIV_FUSED)
