@@ -35,7 +35,6 @@ namespace pk {
 
 namespace {
 constexpr double kLaunchSeconds = 4e-6;
-constexpr double kCacheBytesPerSecond = 12e12;  // aggregate L2/MALL read rate used by the estimate
 constexpr double kHbmBytesPerSecond = 8e12;
 
 int elem_bytes(int dtype) { return dtype == PK_BF16 ? 2 : 4; }
@@ -75,28 +74,34 @@ double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes
 }
 
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K) {
+    // Per compute unit: the busiest one holds ceil(tiles / NCU) tiles, `res`
+    // of them resident at once; each K step of a round costs the larger of
+    // the resident tiles' arithmetic at the unit's rate and one step's
+    // latency.  The rate falls when few wavefronts share a SIMD to hide LDS
+    // and memory latency (full at about three per SIMD), and for MFMA tiles
+    // with the LDS words each output needs (1/tile_m + 1/tile_n).
     const double clock = (m.clock_khz > 0 ? m.clock_khz : 2400000) * 1e3;
+    const int64_t ncu = std::max<int32_t>(m.cu_count, 1);
+    const int wave = m.wave > 0 ? m.wave : 64;
     const int64_t tm = (M + e.tile_m - 1) / e.tile_m, tn = (N + e.tile_n - 1) / e.tile_n;
-    const int64_t tiles = tm * tn;
-    const int64_t occ = blocks_per_cu(m, e);
-    const int64_t slots = (int64_t)m.cu_count * occ;
-    const int64_t rounds = (tiles + slots - 1) / slots;
-    const double flops_tile = 2.0 * e.tile_m * e.tile_n * (double)std::max<int64_t>(K, 1);
-    const double words_per_flop = 1.0 / e.tile_m + 1.0 / e.tile_n;
-    const double eff = e.family == PK_FAMILY_MFMA ? 0.90 / (1.0 + 6.7 * words_per_flop) : 0.6;
-    const double compute_round = occ * flops_tile / (cu_rate(m, e, dtype) * eff * clock);
-    const bool two_stage = e.family == PK_FAMILY_MFMA && !(e.variant & PK_MFMA_SINGLE);
+    const int64_t tiles = std::max<int64_t>(tm * tn, 1);
+    const int64_t per_cu = (tiles + ncu - 1) / ncu;
+    const int64_t res = std::min(blocks_per_cu(m, e), per_cu);
+    const int64_t rounds = (per_cu + res - 1) / res;
     const int bk = e.bk > 0 ? e.bk : 1;
-    const double ksteps = (double)((K + bk - 1) / bk);
-    const double step_latency = (e.variant & PK_VALU_NOLDS) && e.family == PK_FAMILY_VALU ? 0.0
-                                : (two_stage ? 0.6e-6 : 1.2e-6);
-    const double compute = rounds * std::max(compute_round, ksteps * step_latency);
+    const double ksteps = (double)((std::max<int64_t>(K, 1) + bk - 1) / bk);
+    const double flops_step = 2.0 * e.tile_m * e.tile_n * bk;
+    const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
+    const double occupancy = std::min(1.0, std::pow(waves_per_simd / 3.0, 0.25));
+    const bool mfma = e.family == PK_FAMILY_MFMA;
+    const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n)) : 0.6;
+    const double rate = cu_rate(m, e, dtype) * clock * eff * occupancy;
+    const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.3e-6;
+    const double compute = (double)rounds * ksteps * std::max((double)res * flops_step / rate, latency);
     const double es = elem_bytes(dtype);
     const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
-    const double out_bytes = 4.0 * (double)M * N;
-    const double hbm = (es * ((double)M * K + (double)K * N) + out_bytes) / kHbmBytesPerSecond;
-    const double traffic = std::max(tile_bytes / kCacheBytesPerSecond, hbm);
-    return std::max(compute, traffic) + kLaunchSeconds;
+    const double hbm = (es * ((double)M * K + (double)K * N) + 4.0 * (double)M * N) / kHbmBytesPerSecond;
+    return std::max(compute, std::max(tile_bytes / kHbmBytesPerSecond, hbm)) + kLaunchSeconds;
 }
 
 void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out) {
