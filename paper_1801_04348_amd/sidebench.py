@@ -1,0 +1,149 @@
+"""Side benchmarks of the paper's other examples on one GPU, each against
+the HBM roofline (8 TB/s) of its compulsory traffic: matrix transposition
+(Section 5.2, Table 3's order 2^14), matrix addition (Section 1), 1D Jacobi
+(Section 5, Table 2's length 2^15 + 2, and 2^28 + 2) and polynomial division
+(Section 5, Table 4's sizes).  Each reports the CASE pick and the
+exhaustively-best leaf.  bench.py includes them in its JSON line; alone:
+
+    python -m paper_1801_04348_amd.sidebench      # one JSON line
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def madd_section(tbl, pk, torch, inputs, n=16384, reps=10):
+    """Matrix addition (Section 1, Fig. 1) of two order-2^14 float32 matrices:
+    the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
+    traffic (two reads and one write per element) against 8 TB/s."""
+    A = inputs.uniform_f32((n, n), seed=0).cuda()
+    B = inputs.uniform_f32((n, n), seed=1).cuda()
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    out = {"order": n, "bytes": 12 * n * n}
+    for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+        p = pk.pk_select_madd(tbl, "f32", n, n, pol)
+        pk.pk_madd(tbl, p, "f32", A, B, C)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pk.pk_madd(tbl, p, "f32", A, B, C)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / reps * 1e-3
+        out[name] = {"kernel": pk.pk_kernel_name(tbl, p, "f32"), "gbps": round(12 * n * n / s / 1e9, 1),
+                     "frac_hbm": round(12 * n * n / s / 8e12, 4)}
+    return out
+
+
+def jacobi_section(tbl, pk, torch, inputs, steps=4, reps=10):
+    """1D Jacobi (Section 5, Fig. 6): four time steps at the paper's length
+    2^15 + 2 (Table 2; launch-bound: microseconds per step) and at 2^28 + 2
+    (HBM-bound), int32; CASE pick and exhaustively-best leaf, in GB/s of
+    compulsory traffic (8 bytes per interior point and step) against 8 TB/s."""
+    out = {"steps": steps}
+    for label, N in (("n_2^15+2", 2 ** 15 + 2), ("n_2^28+2", 2 ** 28 + 2)):
+        a = inputs.small_int_i32((2 * N,), seed=0).cuda()
+        bytes_ = 8 * (N - 2) * steps
+        row = {"bytes": bytes_}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            p = pk.pk_select_jacobi1d(tbl, "i32", N, pol)
+            pk.pk_jacobi1d(tbl, p, "i32", a, steps)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pk.pk_jacobi1d(tbl, p, "i32", a, steps)
+            e1.record()
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) / reps * 1e-3
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, "i32"), "us": round(s * 1e6, 2),
+                         "gbps": round(bytes_ / s / 1e9, 1), "frac_hbm": round(bytes_ / s / 8e12, 4)}
+        out[label] = row
+        del a
+    return out
+
+
+def polydiv_section(tbl, pk, torch, reps=5):
+    """Polynomial division modulo 2^31 - 1 (Section 5, Fig. 8, Table 4): a
+    dividend of N = M + 100 coefficients by a monic divisor of degree M, for
+    M = 2^13, 2^14, 2^15; CASE pick and exhaustively-best leaf, in
+    microseconds per division and GB/s of compulsory traffic (a, b read and
+    a written once per step: 12 bytes per divisor coefficient and step)."""
+    P = 2147483647
+    out = {"modulus": P}
+    g = torch.Generator().manual_seed(0)
+    for e in (13, 14, 15):
+        M = 2 ** e
+        N = M + 100
+        a0 = torch.randint(0, P, (N,), generator=g, dtype=torch.int64).to(torch.int32).cuda()
+        b = torch.randint(0, P, (M,), generator=g, dtype=torch.int64).to(torch.int32).cuda()
+        a = a0.clone()
+        bytes_ = 12 * M * (N - M)
+        row = {"N": N, "bytes": bytes_}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            p = pk.pk_select_polydiv(tbl, N, M, pol)
+            pk.pk_polydiv(tbl, p, a, b, P)
+            ts = []
+            for _ in range(reps):
+                a.copy_(a0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pk.pk_polydiv(tbl, p, a, b, P)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            s = sorted(ts)[len(ts) // 2]
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, "i32"), "us": round(s * 1e6, 1),
+                         "gbps": round(bytes_ / s / 1e9, 1), "frac_hbm": round(bytes_ / s / 8e12, 5)}
+        out["M_2^%d" % e] = row
+    return out
+
+
+def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
+    """Transposition of an order-2^14 float32 matrix (the paper's Table 3
+    size): the CASE pick and the exhaustively-best leaf, in GB/s of compulsory
+    traffic (one read and one write per element) against 8 TB/s."""
+    A = inputs.uniform_f32((n, n), seed=0).cuda()
+    C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    out = {"order": n, "bytes": 8 * n * n}
+    for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+        p = pk.pk_select_transpose(tbl, "f32", n, n, pol)
+        pk.pk_transpose(tbl, p, "f32", A, C)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pk.pk_transpose(tbl, p, "f32", A, C)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / reps * 1e-3
+        out[name] = {"kernel": pk.pk_kernel_name(tbl, p, "f32"), "gbps": round(8 * n * n / s / 1e9, 1),
+                     "frac_hbm": round(8 * n * n / s / 8e12, 4)}
+    return out
+
+
+def run_all(tbl, pk, torch, inputs):
+    return {"transpose": transpose_section(tbl, pk, torch, inputs), "madd": madd_section(tbl, pk, torch, inputs),
+            "jacobi": jacobi_section(tbl, pk, torch, inputs), "polydiv": polydiv_section(tbl, pk, torch)}
+
+
+def main():
+    import torch
+
+    from paper_1801_04348_amd import pk
+    from tests import inputs
+
+    torch.cuda.init()
+    print(json.dumps(run_all(pk.pk_case_table_build(0), pk, torch, inputs)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
