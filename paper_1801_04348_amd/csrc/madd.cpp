@@ -84,7 +84,8 @@ int pk_select_madd(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, in
             hipStreamCreate(&s);
             hipEventCreate(&e0);
             hipEventCreate(&e1);
-            pkk::MaArgs args{buf, (char *)buf + bytes, (char *)buf + 2 * bytes, N, N, N, (int32_t)M, (int32_t)N};
+            pkk::MaArgs args{buf, (char *)buf + bytes, (char *)buf + 2 * bytes, N, N, N, (int32_t)M, (int32_t)N,
+                             N % 4 == 0};
             double best = std::numeric_limits<double>::infinity();
             for (size_t i = 0; i < c.size(); ++i) {
                 if (launch_ma(tbl->machine, *c[i].e, args, s) != PK_OK) continue;
@@ -139,7 +140,9 @@ int pk_madd(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype
     const KernelEntry *e = nullptr;
     int rc = resolve(tbl, params_or_null, (int)dtype, &q, &e);
     if (rc != PK_OK) return rc;
-    pkk::MaArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N};
+    const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && ((uintptr_t)C % 16 == 0) &&
+                     lda % 4 == 0 && ldb % 4 == 0 && ldc % 4 == 0;
+    pkk::MaArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, vec};
     return launch_ma(tbl->machine, *e, args, (hipStream_t)hip_stream);
 }
 

@@ -47,11 +47,15 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     if (e.family == PK_FAMILY_MFMA) return dtype == PK_BF16 ? 2048.0 : 256.0;
     // VALU: 64 lanes x 4 SIMDs / 4 cycles = 64 multiply-adds per clock for
     // float32; int32 multiplies run at a quarter of that.  The tiled kernel
-    // also reads 1 + s LDS words per s multiply-adds (32 words per clock).
-    const double s = std::max(1, (e.variant & PK_VALU_NOLDS) ? 1 : e.s);
+    // also reads 1 + s LDS words per s multiply-adds, which caps it near 24
+    // multiply-adds per clock, rising slowly with s; the direct kernel is
+    // bound by global/L1 reads (about one multiply-add per clock).
+    const double s = std::max(1, e.s);
     double mads = dtype == PK_I32 ? 16.0 : 64.0;
-    if (!(e.variant & PK_VALU_NOLDS)) mads = std::min(mads, 32.0 * s / (1.0 + s));
-    else mads = std::min(mads, 16.0);  // global/L1 bound
+    if (!(e.variant & PK_VALU_NOLDS))
+        mads = std::min(mads, 24.0 * std::pow(s / (1.0 + s), 0.25));
+    else
+        mads = 1.0;
     return 2.0 * mads * lanes;
 }
 }  // namespace
@@ -94,10 +98,16 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
     const double occupancy = std::min(1.0, std::pow(waves_per_simd / 3.0, 0.25));
     const bool mfma = e.family == PK_FAMILY_MFMA;
-    const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n)) : 0.6;
+    // MFMA: the tile's LDS words per output; VALU: workgroups of fewer than
+    // 256 work-items lose in proportion
+    const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n))
+                            : std::min(1.0, e.threads / 256.0);
     const double rate = cu_rate(m, e, dtype) * clock * eff * occupancy;
-    const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.3e-6;
-    const double compute = (double)rounds * ksteps * std::max((double)res * flops_step / rate, latency);
+    const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.1e-6;
+    // VALU K steps also pay their two barriers per resident workgroup
+    const double overhead = mfma ? 0.0 : 0.4e-6 * (double)res;
+    const double compute =
+        (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
     const double es = elem_bytes(dtype);
     const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
     const double hbm = (es * ((double)M * K + (double)K * N) + 4.0 * (double)M * N) / kHbmBytesPerSecond;

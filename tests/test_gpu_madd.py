@@ -34,6 +34,8 @@ def fit(table):
 
 def run(table, p, dtype, A, B):
     C = torch.full(A.shape, -7, dtype=A.dtype, device="cuda")
+    if A.stride(0) != A.shape[1]:            # same row layout as A: leading dimension 516
+        C = torch.full((A.shape[0], A.stride(0)), -7, dtype=A.dtype, device="cuda")[:, :A.shape[1]]
     pk.pk_madd(table, p, dtype, A, B, C)
     torch.cuda.synchronize()
     return C.cpu()
@@ -41,17 +43,24 @@ def run(table, p, dtype, A, B):
 
 @pytest.fixture(scope="module")
 def ragged():
+    # 517 columns: element accesses; a 514-column view of 516-wide rows:
+    # 16-byte aligned rows (wide accesses) with a partial group at the end
     A = inputs.full_range_i32((333, 517), seed=11)
     B = inputs.full_range_i32((333, 517), seed=12)
     Af = inputs.uniform_f32((333, 517), seed=13)
     Bf = inputs.uniform_f32((333, 517), seed=14)
-    return ((A.cuda(), B.cuda(), om.madd(A, B, "i32")), (Af.cuda(), Bf.cuda(), om.madd(Af, Bf, "f32")))
+    out = [(A.cuda(), B.cuda(), om.madd(A, B, "i32")), (Af.cuda(), Bf.cuda(), om.madd(Af, Bf, "f32"))]
+    Av, Bv = A[:, :516].contiguous().cuda()[:, :514], B[:, :516].contiguous().cuda()[:, :514]
+    Afv, Bfv = Af[:, :516].contiguous().cuda()[:, :514], Bf[:, :516].contiguous().cuda()[:, :514]
+    out += [(Av, Bv, om.madd(A[:, :514], B[:, :514], "i32")), (Afv, Bfv, om.madd(Af[:, :514], Bf[:, :514], "f32"))]
+    return out
 
 
 @pytest.mark.parametrize("bx", [64, 128, 256])
 @pytest.mark.parametrize("by", [1, 2, 4])
 def test_every_leaf_and_program(table, fit, ragged, bx, by):
-    for dt, dtype, (A, B, ref) in ((1, "i32", ragged[0]), (0, "f32", ragged[1])):
+    for dt, dtype, (A, B, ref) in ((1, "i32", ragged[0]), (0, "f32", ragged[1]), (1, "i32", ragged[2]),
+                                   (0, "f32", ragged[3])):
         for s in (1, 2, 4, 8):
             p = pk.params(family=pk.PK_FAMILY_MADD, bx=bx, by=by, s=s)
             leaf, var = pk.pk_case_table_lookup(table, dtype, p)
