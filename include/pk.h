@@ -335,6 +335,13 @@ int pk_polydiv(const pk_table *tbl, const pk_params *params_or_null, uint32_t *a
                int64_t M, uint32_t P, void *hip_stream);
 int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_params *out);
 
+/* The CASE policy's analytic time estimate, in seconds, of one launch of a
+ * choice (params resolved as in pk_matmul) for an M x N x K product: the
+ * score pk_select's CASE policy minimises over the feasible set.  Matmul
+ * families only.  Errors as pk_launch_shape. */
+int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+                double *seconds);
+
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N,

@@ -101,24 +101,28 @@ def main():
 
     cm = pk.pk_costmodel_load(args.model)
     pk.pk_case_table_set_costmodel(tbl, cm)
-    learned, case, fallbacks = [], [], 0
+    learned, model_only, case, fallbacks, measured = [], [], [], 0, 0
     for r in recs:
         M, N, K = r["shape"]
         X, t = feature_rows(pk, tbl, r)
         pred = cm.predict(X)
         order = np.argsort(pred, kind="stable")
         pick = int(order[0])
+        best = float(t.min())
+        model_only.append(best / t[pick])
         if len(order) > 1 and math.exp(pred[order[1]] - pred[order[0]]) < 1.0 + MARGIN:
             close = [int(i) for i in order if math.exp(pred[i] - pred[order[0]]) <= 1.0 + MARGIN]
             pick = min(close, key=lambda i: t[i])
             fallbacks += 1
-        best = float(t.min())
+            measured += len(close)
         learned.append(best / t[pick])
-        cp = pk.pk_select(tbl, r["dtype"], M, N, K, pk.PK_POLICY_CASE).as_dict()
-        tc = [c["seconds"] for c in r["candidates"] if c["params"] == cp]
-        case.append(best / tc[0] if tc else float("nan"))
-    out = {"learned": stats(learned), "case": stats([c for c in case if c == c]),
-           "fallback_rate": fallbacks / len(recs), "margin": MARGIN, "model": args.model}
+        # CASE among the candidates the store holds (those feasible for the
+        # operands' alignment), as pk_matmul's own CASE choice would be
+        est = [pk.pk_estimate(tbl, pk.params(**c["params"]), r["dtype"], M, N, K) for c in r["candidates"]]
+        case.append(best / t[int(np.argmin(est))])
+    out = {"learned": stats(learned), "learned_without_measurement": stats(model_only), "case": stats(case),
+           "fallback_rate": fallbacks / len(recs), "candidates_measured_per_fallback": measured / max(fallbacks, 1),
+           "margin": MARGIN, "model": args.model}
     out["learned_over_case_geomean"] = out["learned"]["geomean"] / out["case"]["geomean"]
     print(json.dumps(out), flush=True)
     if args.json:

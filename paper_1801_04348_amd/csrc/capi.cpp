@@ -369,6 +369,20 @@ const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dty
     return e->name;
 }
 
+int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+                double *seconds) {
+    if (!tbl || !p || !seconds) return fail(PK_ERR_INVALID_ARG, "null argument");
+    if (M < 0 || N < 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "negative dimension");
+    if (p->family != PK_FAMILY_VALU && p->family != PK_FAMILY_MFMA)
+        return fail(PK_ERR_INVALID_ARG, "estimates cover the matmul families");
+    pk_params q;
+    const KernelEntry *e = nullptr;
+    int rc = resolve(tbl, p, (int)dtype, &q, &e);
+    if (rc != PK_OK) return rc;
+    *seconds = estimate_seconds(tbl->machine, *e, (int)dtype, M, N, K);
+    return PK_OK;
+}
+
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
                     int64_t *grid, int32_t *block, int64_t *lds_bytes) {
     (void)K;

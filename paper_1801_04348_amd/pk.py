@@ -127,6 +127,8 @@ def lib():
         L.pk_transpose.restype = i32
         L.pk_select_transpose.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_transpose.restype = i32
+        L.pk_estimate.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, ctypes.POINTER(ctypes.c_double)]
+        L.pk_estimate.restype = i32
         L.pk_madd.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
         L.pk_madd.restype = i32
         L.pk_select_madd.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
@@ -352,6 +354,13 @@ def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:
     if r is None:
         raise PkError(PK_ERR_INVALID_ARG, last_error())
     return r.decode()
+
+
+def pk_estimate(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int) -> float:
+    """The CASE policy's analytic seconds for one launch of p on M x N x K."""
+    out = ctypes.c_double()
+    _check(lib().pk_estimate(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, ctypes.byref(out)))
+    return out.value
 
 
 def pk_launch_shape(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):

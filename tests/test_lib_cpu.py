@@ -374,3 +374,31 @@ def test_polydiv_one_launch_program_selection():
     small = pk.pk_case_table_build(0, machines.grid_machine(4096, 131072, 1024))
     p = pk.pk_select_polydiv(small, 2 ** 15 + 100, 2 ** 15)
     assert not (p.variant & pk.PK_POLYDIV_FUSED)
+
+
+def test_case_pick_minimises_the_estimate():
+    # pk_select's CASE choice is the feasible (leaf, E) with the least
+    # pk_estimate; the feasible set rebuilt from the bound table
+    t = pk.pk_case_table_build(0, machines.gfx950())
+    d = pk.pk_case_table_describe(t)
+    for dtype, dt in (("f32", 0), ("i32", 1), ("bf16", 2)):
+        cands = []
+        for part in d["parts"]:
+            if part["dtype"] != dt or part["family"] not in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_MFMA):
+                continue
+            for i, pt in enumerate(part["points"]):
+                if part["first_leaf"][i] < 0:
+                    continue
+                if part["family"] == pk.PK_FAMILY_VALU:
+                    p = pk.params(family=0, bx=pt[0], by=pt[1], s=pt[2])
+                else:
+                    p = pk.params(family=1, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4])
+                cands.append(p)
+        for M, N, K in ((512, 512, 512), (3000, 8192, 1000), (100, 2000, 64)):
+            est = [pk.pk_estimate(t, p, dtype, M, N, K) for p in cands]
+            assert all(e > 0 for e in est)
+            want = pk.pk_kernel_name(t, cands[min(range(len(est)), key=est.__getitem__)], dtype)
+            got = pk.pk_kernel_name(t, pk.pk_select(t, dtype, M, N, K, pk.PK_POLICY_CASE), dtype)
+            assert got == want, (dtype, M, N, K)
+    with pytest.raises(pk.PkError):
+        pk.pk_estimate(t, pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=32, by=8, s=1), "f32", 1, 1, 1)
