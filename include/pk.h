@@ -342,6 +342,15 @@ int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_
 int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
                 double *seconds);
 
+/* Measured vector-ALU ceiling of the table's device, in operations per
+ * second (a multiply-add counts two): independent multiply-add chains with
+ * no memory traffic, f32 (fused multiply-add) or i32 (32-bit multiply and
+ * add, wrapping), timed with HIP events; the roofline of the VALU matmul
+ * programs.  Synchronous; allocates and frees a small output buffer.
+ * Errors: PK_ERR_INVALID_ARG (null, or a table not bound to a device),
+ * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_HIP. */
+int pk_probe_valu_rate(const pk_table *tbl, pk_dtype dtype, double *ops_per_second);
+
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
  * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N,

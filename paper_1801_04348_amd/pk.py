@@ -127,6 +127,8 @@ def lib():
         L.pk_transpose.restype = i32
         L.pk_select_transpose.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_transpose.restype = i32
+        L.pk_probe_valu_rate.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+        L.pk_probe_valu_rate.restype = i32
         L.pk_estimate.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, ctypes.POINTER(ctypes.c_double)]
         L.pk_estimate.restype = i32
         L.pk_madd.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
@@ -354,6 +356,13 @@ def pk_kernel_name(tbl: Table, p: pk_params, dtype) -> str:
     if r is None:
         raise PkError(PK_ERR_INVALID_ARG, last_error())
     return r.decode()
+
+
+def pk_probe_valu_rate(tbl: Table, dtype) -> float:
+    """Measured vector-ALU multiply-add ceiling, operations per second."""
+    out = ctypes.c_double()
+    _check(lib().pk_probe_valu_rate(tbl.handle, _dt(dtype), ctypes.byref(out)))
+    return out.value
 
 
 def pk_estimate(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int) -> float:

@@ -2,7 +2,8 @@
 the HBM roofline (8 TB/s) of its compulsory traffic: matrix transposition
 (Section 5.2, Table 3's order 2^14), matrix addition (Section 1), 1D Jacobi
 (Section 5, Table 2's length 2^15 + 2, and 2^28 + 2) and polynomial division
-(Section 5, Table 4's sizes).  Each reports the CASE pick and the
+(Section 5, Table 4's sizes), and the VALU matmul programs against their
+measured arithmetic ceiling.  Each reports the CASE pick and the
 exhaustively-best leaf.  bench.py includes them in its JSON line; alone:
 
     python -m paper_1801_04348_amd.sidebench      # one JSON line
@@ -130,9 +131,41 @@ def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
     return out
 
 
+def valu_section(tbl, pk, torch, inputs, reps=20):
+    """The VALU matmul programs against their measured ceiling
+    (pk_probe_valu_rate): int32 1024^3 with small-integer entries and float32
+    256^3, CASE pick and exhaustively-best leaf, in operations per second
+    (2 M N K per product)."""
+    out = {"ceiling_f32_tflops": round(pk.pk_probe_valu_rate(tbl, "f32") / 1e12, 2),
+           "ceiling_i32_tops": round(pk.pk_probe_valu_rate(tbl, "i32") / 1e12, 2)}
+    for dtype, n, gen in (("i32", 1024, inputs.small_int_i32), ("f32", 256, inputs.uniform_f32)):
+        A = gen((n, n), seed=0).cuda()
+        B = gen((n, n), seed=1).cuda()
+        C = torch.empty((n, n), dtype=A.dtype, device="cuda")
+        ceiling = out["ceiling_%s_%s" % (dtype, "tops" if dtype == "i32" else "tflops")] * 1e12
+        row = {}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            p = pk.pk_select(tbl, dtype, n, n, n, pol)
+            pk.pk_matmul(tbl, p, dtype, A, B, C)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pk.pk_matmul(tbl, p, dtype, A, B, C)
+            e1.record()
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) / reps * 1e-3
+            rate = 2.0 * n ** 3 / s
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, dtype), "us": round(s * 1e6, 1),
+                         "tops": round(rate / 1e12, 2), "frac_of_ceiling": round(rate / ceiling, 4)}
+        out["%s_%d" % (dtype, n)] = row
+    return out
+
+
 def run_all(tbl, pk, torch, inputs):
     return {"transpose": transpose_section(tbl, pk, torch, inputs), "madd": madd_section(tbl, pk, torch, inputs),
-            "jacobi": jacobi_section(tbl, pk, torch, inputs), "polydiv": polydiv_section(tbl, pk, torch)}
+            "jacobi": jacobi_section(tbl, pk, torch, inputs), "polydiv": polydiv_section(tbl, pk, torch),
+            "valu": valu_section(tbl, pk, torch, inputs)}
 
 
 def main():
