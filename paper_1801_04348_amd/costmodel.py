@@ -15,8 +15,11 @@ best two predictions are within 5 % every candidate predicted within 5 % of
 the best is measured and the fastest kept; the measurement used is the
 store's own -- and the CASE choice, each scored by its measured time against
 the best measured candidate:  ratio = t_best / t_pick = GF_pick / GF_best.
-Reports the geometric mean, median, 10th percentile and worst ratio and the
-fallback rate.
+The CASE choice is the candidate with the least pk_estimate among those the
+store holds (the ones feasible for the operands' alignment).  Reports the
+geometric mean, median, 10th percentile and worst ratio, the same for the
+model's own pick without measurement, the fallback rate, and the
+prediction latency per shape (one launch over the shape's candidates).
 """
 from __future__ import annotations
 
@@ -91,21 +94,28 @@ def main():
         Xs, ts = zip(*(feature_rows(pk, tbl, r) for r in recs))
         X = np.concatenate(Xs).astype(np.float32)
         t = np.concatenate(ts)
+        import time
+        t0 = time.perf_counter()
         cm, loss = pk.pk_costmodel_train(tbl, X, t, epochs=args.epochs, lr=args.lr, seed=args.seed)
+        train_s = time.perf_counter() - t0
         pred = cm.predict(X)
         rmse = float(np.sqrt(np.mean((pred - np.log(t)) ** 2)))
         cm.save(args.out)
         print(json.dumps({"rows": int(X.shape[0]), "shapes": len(recs), "epochs": args.epochs, "lr": args.lr,
-                          "loss_standardised": loss, "rmse_ln_seconds": rmse, "model": args.out}), flush=True)
+                          "loss_standardised": loss, "rmse_ln_seconds": rmse, "train_seconds": round(train_s, 3),
+                          "ms_per_epoch": round(train_s / args.epochs * 1e3, 4), "model": args.out}), flush=True)
         return
 
     cm = pk.pk_costmodel_load(args.model)
     pk.pk_case_table_set_costmodel(tbl, cm)
-    learned, model_only, case, fallbacks, measured = [], [], [], 0, 0
+    import time
+    learned, model_only, case, fallbacks, measured, infer = [], [], [], 0, 0, []
     for r in recs:
         M, N, K = r["shape"]
         X, t = feature_rows(pk, tbl, r)
+        t0 = time.perf_counter()
         pred = cm.predict(X)
+        infer.append(time.perf_counter() - t0)
         order = np.argsort(pred, kind="stable")
         pick = int(order[0])
         best = float(t.min())
@@ -122,7 +132,7 @@ def main():
         case.append(best / t[int(np.argmin(est))])
     out = {"learned": stats(learned), "learned_without_measurement": stats(model_only), "case": stats(case),
            "fallback_rate": fallbacks / len(recs), "candidates_measured_per_fallback": measured / max(fallbacks, 1),
-           "margin": MARGIN, "model": args.model}
+           "margin": MARGIN, "predict_ms_per_shape": round(1e3 * sum(infer) / len(infer), 4), "model": args.model}
     out["learned_over_case_geomean"] = out["learned"]["geomean"] / out["case"]["geomean"]
     print(json.dumps(out), flush=True)
     if args.json:
