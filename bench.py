@@ -151,7 +151,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--policy", choices=["auto", "case", "learned"], default="auto",
                     help="auto: the learned cost model when one for this machine is shipped, else the case table")
-    ap.add_argument("--no-grouped", action="store_true", help="skip the side sections: grouped products, transposition, matrix addition, 1D Jacobi, polynomial division")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run the timed sweep only: skip the untimed sections (exhaustive comparison, grouped "
+                         "products, side benchmarks), e.g. for a profile of the sweep's kernels alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--machine", default=None,
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
@@ -289,7 +291,7 @@ def main():
     # machine), the CASE pick and the LEARNED pick (untimed for `value`)
     exhaustive = None
     best = {}
-    if os.path.exists(TUNED):
+    if os.path.exists(TUNED) and not args.sweep_only:
         with open(TUNED) as f:
             tuned = json.load(f)
         if tuned["machine"]["regs_block"] == machine["regs_block"]:
@@ -333,11 +335,11 @@ def main():
                                "learned_fallback_rate": round(fb / max(sel, 1), 3)})
 
     side = None
-    if not args.no_grouped:
+    if not args.sweep_only:
         from paper_1801_04348_amd import sidebench
         side = sidebench.run_all(tbl, pk, torch, inputs)
     grouped = None
-    if not args.no_grouped:
+    if not args.sweep_only:
         grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,

@@ -240,10 +240,13 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
  * strides over the configuration's tiles of all its products.  Sizes and
  * pointer arrays are host arrays (device pointers inside), all of length G;
  * products with M or N = 0 are skipped.  per_group_or_null gives each
- * product's MFMA leaf/parameters (resolved as in pk_matmul); NULL chooses
- * per product with `policy` (PK_POLICY_CASE, or PK_POLICY_LEARNED when the
- * table has a cost model) among the MFMA candidates that have grouped
- * instances.  Rows that are not aligned for the 16-byte loads are read with
+ * product's MFMA leaf/parameters (resolved as in pk_matmul); NULL runs one
+ * program for all products -- among the MFMA candidates with grouped
+ * instances that fit every product, the one whose tiles cost the least
+ * compute-unit time summed over the products under the CASE policy's model
+ * (one launch; the latency of a single product does not count when the
+ * products run side by side).  `policy` is PK_POLICY_CASE or
+ * PK_POLICY_LEARNED; both make that choice.  Rows that are not aligned for the 16-byte loads are read with
  * element loads.  The plan copies its descriptors to the device when created
  * (allocating and synchronizing then); running it allocates nothing and does
  * not synchronize, so it may be captured in a HIP graph.  Pointers must stay

@@ -63,8 +63,7 @@ TR_S = (1, 2, 4, 8)
 MFMA_F32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (128, 128, 32, 2, 2),
             (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4)]
 MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128, 128, 64, 2, 2),
-             (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4),
-             (64, 64, 128, 2, 2), (128, 64, 128, 2, 2), (64, 128, 128, 2, 2), (128, 128, 128, 2, 2)]
+             (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4)]
 
 
 def valu_lds(bx, by, s, nolds):

@@ -79,9 +79,8 @@ const MfmaPoint kMfmaF32[] = {
     {256, 128, 32, 4, 2}, {128, 256, 32, 2, 4}, {256, 256, 32, 4, 4},
 };
 const MfmaPoint kMfmaBf16[] = {
-    {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},   {128, 128, 64, 2, 2},
-    {256, 128, 64, 4, 2}, {128, 256, 64, 2, 4}, {256, 256, 64, 4, 4},  {64, 64, 128, 2, 2},
-    {128, 64, 128, 2, 2}, {64, 128, 128, 2, 2}, {128, 128, 128, 2, 2},
+    {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},  {128, 128, 64, 2, 2},
+    {256, 128, 64, 4, 2}, {128, 256, 64, 2, 4}, {256, 256, 64, 4, 4},
 };
 
 struct Syms {

@@ -1,8 +1,10 @@
 // Many independent products in one persistent launch per tile configuration.
 //
 // A plan fixes, once, everything a grouped launch needs: for every product its
-// leaf and program parameters (given, or chosen by the table's selection
-// policy among the MFMA points that have grouped instances), its descriptor
+// leaf and program parameters (given per product, or else one program for
+// all of them: among the MFMA points with grouped instances that fit every
+// product, the one whose tiles cost the least compute-unit time in total),
+// its descriptor
 // (pointers, leading dimensions, sizes, whether rows are aligned for the wide
 // loads, first global tile index), and a tile -> product map.  Products are
 // partitioned by tile configuration; each part is one persistent launch whose
@@ -76,6 +78,8 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
         return fail(PK_ERR_INVALID_ARG, "null argument or negative group count");
     if (dtype != PK_F32 && dtype != PK_BF16) return fail(PK_ERR_UNSUPPORTED_DTYPE, "grouped products: f32 or bf16");
     if (tbl->device < 0) return fail(PK_ERR_INVALID_ARG, "grouped plans need a table bound to a device");
+    if (policy != PK_POLICY_CASE && policy != PK_POLICY_LEARNED)
+        return fail(PK_ERR_INVALID_ARG, "grouped plans: policy CASE or LEARNED");
     *out = nullptr;
     try {
         std::unique_ptr<pk_grouped_plan> plan(new pk_grouped_plan);
@@ -104,19 +108,30 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
             if (okc[g].empty())
                 return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no grouped program fits product " + std::to_string(g));
         }
-        std::vector<float> pred;
-        const bool learned = !per_group_or_null && policy == PK_POLICY_LEARNED && tbl->costmodel;
-        if (learned) {
-            std::vector<float> X;
-            for (int g = 0; g < G; ++g)
+        // one program for the whole plan: the one whose tiles cost the least
+        // compute-unit time summed over the products (a persistent launch runs
+        // products side by side, so per-product launch latency does not
+        // count; one launch instead of one per program chosen)
+        const KernelEntry *plan_entry = nullptr;
+        if (!per_group_or_null) {
+            std::map<const KernelEntry *, std::pair<double, int>> total;  // work, products it fits
+            int live = 0;
+            for (int g = 0; g < G; ++g) {
+                if (M[g] == 0 || N[g] == 0) continue;
+                ++live;
                 for (const auto &c : okc[g]) {
-                    X.resize(X.size() + PK_NFEATURES);
-                    features(tbl->machine, *c.entry, M[g], N[g], K[g], &X[X.size() - PK_NFEATURES]);
+                    auto &t = total[c.entry];
+                    t.first += tile_work_seconds(tbl->machine, *c.entry, (int)dtype, M[g], N[g], K[g]);
+                    t.second += 1;
                 }
-            pred.resize(X.size() / PK_NFEATURES);
-            costmodel_predict(*tbl->costmodel, tbl->device, X.data(), (int64_t)pred.size(), pred.data());
+            }
+            double best = 0.0;
+            for (const auto &kv : total)
+                if (kv.second.second == live && (!plan_entry || kv.second.first < best)) {
+                    plan_entry = kv.first;
+                    best = kv.second.first;
+                }
         }
-        size_t row = 0;
         for (int g = 0; g < G; ++g) {
             if (M[g] == 0 || N[g] == 0) continue;
             pk_params p;
@@ -131,12 +146,10 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
                 p = q;
             } else {
                 const auto &ok = okc[g];
-                int pick = 0;
-                for (size_t i = 1; i < ok.size(); ++i) {
-                    const bool better = learned ? pred[row + i] < pred[row + pick] : ok[i].estimate < ok[pick].estimate;
-                    if (better) pick = (int)i;
-                }
-                row += ok.size();
+                int pick = -1;
+                for (size_t i = 0; i < ok.size(); ++i)
+                    if (ok[i].entry == plan_entry) pick = (int)i;
+                if (pick < 0) return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no grouped program fits every product");
                 fill_params(tbl, ok[pick], (int)dtype, &p);
             }
             std::vector<int64_t> pt;

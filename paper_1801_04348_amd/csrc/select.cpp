@@ -114,6 +114,28 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     return std::max(compute, std::max(tile_bytes / kHbmBytesPerSecond, hbm)) + kLaunchSeconds;
 }
 
+double tile_work_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K) {
+    // compute-unit seconds of the product's tiles when the unit is kept full
+    // of this program's workgroups: a unit advances its resident tiles by one
+    // K step in max(res * flops_step / rate, latency)
+    const double clock = (m.clock_khz > 0 ? m.clock_khz : 2400000) * 1e3;
+    const int wave = m.wave > 0 ? m.wave : 64;
+    const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
+    const int64_t res = blocks_per_cu(m, e);
+    const int bk = e.bk > 0 ? e.bk : 1;
+    const double ksteps = (double)((std::max<int64_t>(K, 1) + bk - 1) / bk);
+    const double flops_step = 2.0 * e.tile_m * e.tile_n * bk;
+    const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
+    const double occupancy = std::min(1.0, std::pow(waves_per_simd / 3.0, 0.25));
+    const bool mfma = e.family == PK_FAMILY_MFMA;
+    const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n))
+                            : std::min(1.0, e.threads / 256.0);
+    const double rate = cu_rate(m, e, dtype) * clock * eff * occupancy;
+    const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.1e-6;
+    const double step = std::max((double)res * flops_step / rate, latency);
+    return (double)tiles * ksteps * step / (double)res;
+}
+
 void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out) {
     const pk_table::Part *part = tbl->part(c.family, dtype);
     point_params(c.family, part->fam.points[c.point], out);

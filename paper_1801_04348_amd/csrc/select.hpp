@@ -27,6 +27,11 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
 // Analytic time of one launch (the CASE score).
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K);
 
+// Compute-unit seconds of a product's tiles under a program when every
+// compute unit is kept full of its workgroups (the work a persistent grouped
+// launch spends on the product).
+double tile_work_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K);
+
 // Analytic time of one launch of a streaming (HBM-bound) kernel moving
 // `bytes`: compulsory bytes over 8 TB/s, scaled by the share one launch can
 // sustain -- the filled share of the last round of tiles, the bytes a compute
