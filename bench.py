@@ -159,7 +159,9 @@ def main():
                     help="bind the case table to this recorded machine descriptor (JSON) instead of the runtime's")
     ap.add_argument("--save-machine", default=None, help="write the machine descriptor the table was bound to")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a 256 MiB device copy three times (known bytes, for counter calibration)")
+                    help="run a 256 MiB device copy three times first (known bytes, for counter calibration), then "
+                         "once right before and once right after the timed steps (they delimit the timed "
+                         "region's dispatches in a profile; see paper_1801_04348_amd/profwindow.py)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the product path has no multi-GPU part; run with --gpus 1",
@@ -198,13 +200,17 @@ def main():
     Abuf = inputs.uniform_f32((big * big,), seed=0).cuda()
     Bbuf = inputs.uniform_f32((big * big,), seed=1).cuda()
     Cbuf = torch.empty((big * big,), dtype=torch.float32, device="cuda")
+    marker = None
     if args.calibrate_copy:
         src_t = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst_t = torch.empty_like(src_t)
-        for _ in range(3):
+
+        def marker():
             torch.add(src_t, 0.0, out=dst_t)
+
+        for _ in range(3):
+            marker()
         torch.cuda.synchronize()
-        del src_t, dst_t
     ops = []
     for (M, N, K) in shapes:
         p = pk.pk_select(tbl, "f32", M, N, K, policy, allow_fallback=True)
@@ -254,12 +260,17 @@ def main():
     pool = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(n_dom * args.steps)]
     recorded = []
+    if marker:
+        marker()  # the fourth copy: the timed region's launches follow it
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         one_pass(pool)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if marker:
+        marker()  # the fifth copy closes the window
+        torch.cuda.synchronize()
     value = flops_step * args.steps / elapsed / 1e9
     dom_flops = sum(o["flops"] for o, _, _ in recorded)
     dom_bytes = sum(4.0 * (o["M"] * o["K"] + o["K"] * o["N"] + o["M"] * o["N"]) for o, _, _ in recorded)

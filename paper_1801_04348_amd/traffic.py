@@ -5,15 +5,17 @@ Two counter passes over the benchmark command, one counter each (each pass a
 run of its own), with the calibration copy switched on:
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o fetch -- \\
-        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --machine M.json --calibrate-copy
+        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --sweep-only --machine M.json --calibrate-copy
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o write -- \\
-        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --machine M.json --calibrate-copy
+        python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --sweep-only --machine M.json --calibrate-copy
     python3 paper_1801_04348_amd/traffic.py --fetch D1 --write D2 --kernel NAME --out profiles/traffic_NAME.json
 
 The calibration copy (a float32 add of zero over 256 MiB: reads 256 MiB and
 writes 256 MiB) gives, per counter, factor = known bytes / counter bytes; the
-kernel's bytes per launch are its mean counter value over all its launches
-(in KiB per dispatch) times that factor.  The result records a hash of the
+kernel's bytes per launch are its mean counter value (in KiB per dispatch)
+over its launches in the timed region -- the dispatches between the fourth
+and fifth copy (see profwindow.py), the launches the benchmark's `achieved`
+averages over -- times that factor.  The result records a hash of the
 kernel sources so the benchmark ignores it once the kernels change.
 """
 from __future__ import annotations
@@ -27,6 +29,9 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+import profwindow  # noqa: E402
 COPY_BYTES = 256 << 20
 KERNEL_SOURCES = ("csrc/kernels/mfma.hpp", "csrc/kernels/valu.hpp", "csrc/kernels/kargs.hpp")
 
@@ -40,6 +45,8 @@ def kernel_source_hash() -> str:
 
 
 def counter_per_dispatch(d, counter):
+    """[(dispatch id, kernel name, counter value summed over instances)] in
+    dispatch order."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit("no counter_collection.csv under %s" % d)
@@ -49,9 +56,9 @@ def counter_per_dispatch(d, counter):
             for r in csv.DictReader(f):
                 if r.get("Counter_Name") != counter:
                     continue
-                key = (fn, int(r.get("Dispatch_Id", 0)), r.get("Kernel_Name", ""))
+                key = (int(r.get("Dispatch_Id", 0)), r.get("Kernel_Name", ""))
                 per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
-    return [(k[2], v) for k, v in sorted(per.items())]
+    return [(k[0], k[1], v) for k, v in sorted(per.items())]
 
 
 def main():
@@ -65,8 +72,11 @@ def main():
     total = 0.0
     for counter, d in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
         rows = counter_per_dispatch(d, counter)
-        copies = sorted(v for name, v in rows if not name.startswith("pk_") and v * 1024 > COPY_BYTES / 4)
-        kern = [v for name, v in rows if name == args.kernel]
+        big = lambda r: r["value"] * 1024 > COPY_BYTES / 4  # noqa: E731
+        recs = [{"Dispatch_Id": i, "Kernel_Name": name, "value": v} for i, name, v in rows]
+        copies = sorted(r["value"] for r in recs if not r["Kernel_Name"].startswith("pk_") and big(r))
+        # the timed region's launches only (between the fourth and fifth copy)
+        kern = [r["value"] for r in profwindow.timed_window(recs, big=big) if r["Kernel_Name"] == args.kernel]
         if not copies or not kern:
             raise SystemExit("missing calibration copies or %s dispatches for %s" % (args.kernel, counter))
         copy_kib = copies[len(copies) // 2]

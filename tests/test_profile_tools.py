@@ -1,0 +1,75 @@
+"""Host logic of the profile tools: the timed-region window between the
+benchmark's marker copies, and the calibrated traffic per launch."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_1801_04348_amd import profwindow
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctor_add<float> >"
+
+
+def trace_rows():
+    # 3 calibration copies, warm-up and selection launches, marker, timed
+    # launches, marker, more launches
+    names = [COPY] * 3 + ["pk_a", "pk_b", "pk_a"] + [COPY] + ["pk_a", "pk_b", "pk_a"] + [COPY] + ["pk_a"]
+    rows, t = [], 0
+    for i, n in enumerate(names):
+        d = 100_000 if n == COPY else (1000 if n == "pk_a" else 3000) + (500 if 7 <= i <= 9 else 0)
+        rows.append({"Dispatch_Id": str(i + 1), "Kernel_Name": n, "Start_Timestamp": str(t),
+                     "End_Timestamp": str(t + d)})
+        t += d + 10
+    return rows
+
+
+def test_window_is_between_fourth_and_fifth_copy():
+    rows = trace_rows()
+    import random
+    random.Random(0).shuffle(rows)              # dispatch order, not file order, decides
+    win = profwindow.timed_window(rows)
+    assert [r["Dispatch_Id"] for r in win] == ["8", "9", "10"]
+    with pytest.raises(SystemExit):
+        profwindow.timed_window(trace_rows()[:8])
+
+
+def test_window_cli_stats(tmp_path):
+    p = tmp_path / "k_kernel_trace.csv"
+    rows = trace_rows()
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "paper_1801_04348_amd", "profwindow.py"),
+                          "--trace", str(p)], capture_output=True, text=True, check=True)
+    res = json.loads(out.stdout)
+    by = {k["kernel"]: k for k in res["kernels"]}
+    assert res["dispatches"] == 3
+    assert by["pk_a"]["calls"] == 2 and by["pk_a"]["average_us"] == 1.5
+    assert by["pk_b"]["calls"] == 1 and by["pk_b"]["average_us"] == 3.5
+
+
+def test_traffic_scaled_by_the_copy(tmp_path):
+    # FETCH reads half the copy's true bytes -> factor 2; WRITE exact -> factor 1
+    copy_kib = (256 << 20) / 1024
+    for counter, cdir, copy_val, kern_val in (("FETCH_SIZE", "f", copy_kib / 2, 100.0), ("WRITE_SIZE", "w", copy_kib, 40.0)):
+        d = tmp_path / cdir
+        d.mkdir()
+        names = ["copy"] * 3 + ["pk_k", "pk_k"] + ["copy"] + ["pk_k", "pk_k"] + ["copy"] + ["pk_k"]
+        with open(d / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for i, n in enumerate(names):
+                v = copy_val if n == "copy" else (kern_val if 6 <= i <= 7 else 999.0)
+                w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": n, "Counter_Name": counter, "Counter_Value": v})
+    out = tmp_path / "t.json"
+    subprocess.run([sys.executable, os.path.join(ROOT, "paper_1801_04348_amd", "traffic.py"), "--fetch",
+                    str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--kernel", "pk_k", "--out", str(out)],
+                   capture_output=True, text=True, check=True)
+    res = json.load(open(out))
+    assert res["FETCH_SIZE"]["launches"] == 2 and res["FETCH_SIZE"]["factor"] == 2.0
+    assert res["bytes_per_launch"] == 100.0 * 1024 * 2 + 40.0 * 1024
