@@ -45,14 +45,21 @@ def timed_window(rows, key="Dispatch_Id", name_key="Kernel_Name", big=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True, help="rocprofv3 *_kernel_trace.csv")
+    ap.add_argument("--all", action="store_true",
+                    help="every library dispatch of the trace, not the timed window (runs without markers)")
+    ap.add_argument("--by-grid", action="store_true",
+                    help="one line per kernel and grid size (the same kernel on different problem sizes)")
     args = ap.parse_args()
     with open(args.trace) as f:
         rows = list(csv.DictReader(f))
-    win = timed_window(rows)
+    win = [r for r in rows if r["Kernel_Name"].startswith("pk_")] if args.all else timed_window(rows)
     stats = {}
     for r in win:
         d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-        s = stats.setdefault(r["Kernel_Name"], [0, 0, None, 0])
+        key = r["Kernel_Name"]
+        if args.by_grid:
+            key += " grid=%s" % r.get("Grid_Size_X", r.get("Grid_Size", "?"))
+        s = stats.setdefault(key, [0, 0, None, 0])
         s[0] += 1
         s[1] += d
         s[2] = d if s[2] is None else min(s[2], d)
