@@ -42,7 +42,7 @@ extern "C" {
 
 /* ------------------------------------------------------------------ errors */
 #define PK_OK 0
-#define PK_ERR_INVALID_ARG -1         /* null pointer, negative size, ld too small, misaligned */
+#define PK_ERR_INVALID_ARG -1         /* null pointer, negative size, ld too small */
 #define PK_ERR_NO_FEASIBLE_BRANCH -2  /* no leaf of the case table holds (refuse with no strategy left) */
 #define PK_ERR_UNSUPPORTED_DTYPE -3   /* the dtype has no kernel in the requested family */
 #define PK_ERR_NOT_INSTANTIATED -4    /* parameters satisfy the constraints but no compiled instance exists */
@@ -210,8 +210,9 @@ int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t
  * about 20 ms (at least 3 launches); seconds_out[i] is its mean time per
  * launch.  Runs on a private stream and synchronizes.  *n receives the number
  * of candidates; arrays must hold cap >= *n entries (else
- * PK_ERR_BUFFER_TOO_SMALL).  MFMA candidates are left out when the given
- * operands are not aligned for them.
+ * PK_ERR_BUFFER_TOO_SMALL).  MFMA candidates are timed on the given
+ * operands as they are: rows not aligned for 16-byte loads are read element
+ * by element.
  * Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_HIP. */
 int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                int64_t ldc, int64_t M, int64_t N, int64_t K, pk_params *params_out, double *seconds_out, int cap,
@@ -228,7 +229,11 @@ int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, 
  *                       (the "forced" mode used to test every program),
  *   both < 0            looks the leaf up at E.
  * M == 0 or N == 0 is a no-op; K == 0 writes zeros (or leaves C unchanged
- * when accumulating).  Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
+ * when accumulating).  MFMA programs load 16 bytes at a time along rows that
+ * are aligned for it (f32: A and B 16-byte aligned, lda and ldb multiples of
+ * 4; bf16: A 16-byte aligned with lda a multiple of 8, B 4-byte aligned with
+ * ldb even) and element by element otherwise -- the same arithmetic in the
+ * same order, so the result does not depend on the alignment.  Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
  * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NOT_INSTANTIATED, PK_ERR_HIP. */
 int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype,
               const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,

@@ -101,24 +101,11 @@ int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N)
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-int check_data(const KernelEntry &e, int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
-    if (e.family != PK_FAMILY_MFMA) return PK_OK;
-    // 16-byte global loads along rows
-    const int64_t vec = dtype == PK_BF16 ? 8 : 4;
-    if (!aligned16(A) || lda % vec != 0)
-        return fail(PK_ERR_INVALID_ARG, "MFMA leaves need 16-byte aligned A rows (lda multiple of " +
-                                            std::to_string(vec) + ")");
-    if (dtype == PK_BF16) {
-        if (((uintptr_t)B & 3u) != 0 || ldb % 2 != 0)
-            return fail(PK_ERR_INVALID_ARG, "MFMA bf16 leaves need 4-byte aligned B column pairs (even ldb)");
-    } else if (!aligned16(B) || ldb % 4 != 0) {
-        return fail(PK_ERR_INVALID_ARG, "MFMA f32 leaves need 16-byte aligned B rows (ldb multiple of 4)");
-    }
-    return PK_OK;
-}
-
-bool data_ok(int family, int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
-    if (family != PK_FAMILY_MFMA) return true;
+// Rows aligned for the MFMA programs' wide loads: 16-byte loads along the
+// rows of A (lda a multiple of 4 f32 / 8 bf16 elements) and of B (f32), or
+// 4-byte column pairs of B (bf16).  Otherwise the programs read element by
+// element (same arithmetic, same summation order).
+bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
     const int64_t vec = dtype == PK_BF16 ? 8 : 4;
     if (!aligned16(A) || lda % vec != 0) return false;
     if (dtype == PK_BF16) return ((uintptr_t)B & 3u) == 0 && ldb % 2 == 0;
@@ -425,9 +412,8 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
         const KernelEntry *e = nullptr;
         int rc = resolve(tbl, params_or_null, (int)dtype, &q, &e);
         if (rc != PK_OK) return rc;
-        rc = check_data(*e, (int)dtype, A, lda, B, ldb);
-        if (rc != PK_OK) return rc;
-        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0};
+        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0,
+                    wide_rows((int)dtype, A, lda, B, ldb) ? 1 : 0};
         return launch(tbl->machine, *e, args, (hipStream_t)hip_stream);
     } catch (const std::exception &ex) {
         return fail(PK_ERR_INVALID_ARG, ex.what());

@@ -60,7 +60,7 @@ static bool grouped_instance(int dtype, int variant, const std::vector<int64_t> 
 }
 
 static bool aligned_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
-    return data_ok(PK_FAMILY_MFMA, dtype, A, lda, B, ldb);
+    return wide_rows(dtype, A, lda, B, ldb);
 }
 
 }  // namespace pk

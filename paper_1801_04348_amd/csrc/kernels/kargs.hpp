@@ -15,6 +15,7 @@ struct MmArgs {
     int64_t lda, ldb, ldc;
     int32_t M, N, K;
     int32_t accumulate;
+    int32_t vec;  // MFMA programs: rows aligned for 16-byte loads (else element loads)
 };
 
 // One product of a grouped launch.

@@ -369,14 +369,14 @@ template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, true);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, a.vec != 0);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, true);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, a.vec != 0);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
@@ -389,7 +389,7 @@ __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
         const GroupDesc &d = g.descs[g.tile_group[t]];
         const int64_t local = t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate};
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
         mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
     }
@@ -401,7 +401,7 @@ __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
         const GroupDesc &d = g.descs[g.tile_group[t]];
         const int64_t local = t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate};
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
         mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
     }

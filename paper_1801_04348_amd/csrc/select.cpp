@@ -77,7 +77,8 @@ double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes
     return bytes * (tiles >= ncu ? imbalance : 1.0) / bw + 0.5e-6 * rounds + 3e-6;
 }
 
-double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K) {
+double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K,
+                        bool wide) {
     // Per compute unit: the busiest one holds ceil(tiles / NCU) tiles, `res`
     // of them resident at once; each K step of a round costs the larger of
     // the resident tiles' arithmetic at the unit's rate and one step's
@@ -106,8 +107,11 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.1e-6;
     // VALU K steps also pay their two barriers per resident workgroup
     const double overhead = mfma ? 0.0 : 0.4e-6 * (double)res;
+    // element loads instead of 16-byte loads (rows not aligned): measured
+    // about 1.3x (f32) and 1.5x (bf16) slower per step
+    const double narrow = (mfma && !wide) ? (dtype == PK_BF16 ? 1.5 : 1.3) : 1.0;
     const double compute =
-        (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
+        narrow * (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
     const double es = elem_bytes(dtype);
     const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
     const double hbm = (es * ((double)M * K + (double)K * N) + 4.0 * (double)M * N) / kHbmBytesPerSecond;
@@ -149,7 +153,8 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
     for (int family : {PK_FAMILY_VALU, PK_FAMILY_MFMA}) {  // the product families
         const pk_table::Part *part = tbl->part(family, dtype);
         if (!part || !part->supported) continue;
-        if (A && !data_ok(family, dtype, A, lda, B, ldb)) continue;
+        // MFMA programs read unaligned rows element by element: feasible, slower
+        const bool wide = !A || family != PK_FAMILY_MFMA || wide_rows(dtype, A, lda, B, ldb);
         for (size_t i = 0; i < part->fam.points.size(); ++i) {
             const int leaf = part->first_leaf[i];
             if (leaf < 0) continue;
@@ -160,7 +165,7 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
             c.variant = (int)part->solved.leaves[leaf].applied;
             c.entry = find_instance(family, c.variant, dtype, part->fam.points[i]);
             if (!c.entry) continue;
-            c.estimate = estimate_seconds(tbl->machine, *c.entry, dtype, M, N, K);
+            c.estimate = estimate_seconds(tbl->machine, *c.entry, dtype, M, N, K, wide);
             out.push_back(c);
         }
     }
@@ -175,7 +180,7 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
     if (err != hipSuccess) throw std::runtime_error(std::string("hipSetDevice: ") + hipGetErrorString(err));
     const size_t es = dtype == PK_BF16 ? 2 : 4;
     void *sA = nullptr, *sB = nullptr, *sC = nullptr;
-    MmArgs args{nullptr, nullptr, nullptr, K, N, N, (int32_t)M, (int32_t)N, (int32_t)K, 0};
+    MmArgs args{nullptr, nullptr, nullptr, K, N, N, (int32_t)M, (int32_t)N, (int32_t)K, 0, 0};
     if (ops && ops->A) {
         args.A = ops->A;
         args.B = ops->B;
@@ -199,6 +204,7 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
         args.B = sB;
         args.C = sC;
     }
+    args.vec = wide_rows(dtype, args.A, args.lda, args.B, args.ldb) ? 1 : 0;
     hipStream_t s;
     hipEvent_t e0, e1;
     hipStreamCreate(&s);

@@ -25,7 +25,9 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
                                 int64_t ldb = 0);
 
 // Analytic time of one launch (the CASE score).
-double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K);
+// `wide`: the operands' rows are aligned for the MFMA programs' 16-byte loads.
+double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K,
+                        bool wide = true);
 
 // Compute-unit seconds of a product's tiles under a program when every
 // compute unit is kept full of its workgroups (the work a persistent grouped
@@ -63,7 +65,7 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
 // helpers shared with capi.cpp
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);
 int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
-bool data_ok(int family, int dtype, const void *A, int64_t lda, const void *B, int64_t ldb);
+bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb);
 int launch(const pk_machine &m, const KernelEntry &e, const MmArgs &args, hipStream_t stream);
 void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out);
 int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pout, const KernelEntry **entry);

@@ -316,15 +316,36 @@ def test_empty_output_is_noop(table):
     torch.cuda.synchronize()
 
 
-def test_unaligned_rows_refused_by_mfma_but_case_pick_runs(table, desc):
-    M, N, K = 64, 64, 33           # lda = 33: rows not 16-byte aligned
-    A = inputs.uniform_f32((M, K), seed=71)
-    B = inputs.uniform_f32((K, N), seed=72)
-    with pytest.raises(pk.PkError) as e:
-        run(table, mfma_params(mfma_points(desc, "f32")[0], 0), "f32", dev(A), dev(B), M, N)
-    assert e.value.code == pk.PK_ERR_INVALID_ARG
-    C = run(table, None, "f32", dev(A), dev(B), M, N)  # CASE skips MFMA here
-    assert rel_fro(C.numpy(), om.matmul(A, B, "f32")) <= F32_TOL
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_unaligned_rows_take_element_loads(table, fit, desc, dtype):
+    # operands one element off 16-byte alignment with odd leading dimensions:
+    # every MFMA program reads them element by element, with the same tile
+    # arithmetic, so the result is bit-identical to the aligned run
+    M, N, K = 131, 70, 45
+    if dtype == "f32":
+        A = inputs.uniform_f32((M, K), seed=71)
+        B = inputs.uniform_f32((K, N), seed=72)
+    else:
+        A = inputs.bf16_bits(inputs.uniform_f32((M, K), seed=71))
+        B = inputs.bf16_bits(inputs.uniform_f32((K, N), seed=72))
+    ref = om.matmul(A, B, dtype)
+    Au = dev(torch.cat([A.new_zeros((M, 1)), A, A.new_zeros((M, 2))], dim=1))[:, 1:K + 1]   # lda = K + 3
+    Bu = dev(torch.cat([B.new_zeros((K, 1)), B, B.new_zeros((K, 2))], dim=1))[:, 1:N + 1]   # ldb = N + 3
+    Kp, Np = (K + 7) // 8 * 8, (N + 7) // 8 * 8
+    Aa = dev(torch.cat([A, A.new_zeros((M, Kp - K))], dim=1))[:, :K]
+    Ba = dev(torch.cat([B, B.new_zeros((K, Np - N))], dim=1))[:, :N]
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    for pt in mfma_points(desc, dtype):
+        for v in MFMA_VARIANTS:
+            say("mfma %s unaligned %s variant %d" % (dtype, pt, v))
+            Cu = forced(table, fit, 1, dtype, v, pt, mfma_params(pt, v), Au, Bu, M, N)
+            if Cu is None:
+                continue
+            Ca = forced(table, fit, 1, dtype, v, pt, mfma_params(pt, v), Aa, Ba, M, N)
+            assert rel_fro(Cu.numpy(), ref) <= tol, (pt, v)
+            assert np.array_equal(Cu.numpy(), Ca.numpy()), (pt, v)
+    C = run(table, None, dtype, Au, Bu, M, N)            # the CASE pick on these operands
+    assert rel_fro(C.numpy(), ref) <= tol
 
 
 # ---------------------------------------------------------------- full sizes, CASE pick (as benchmarked)
