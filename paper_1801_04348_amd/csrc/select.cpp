@@ -46,12 +46,12 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     const double lanes = (double)threads / (double)(wave * ((threads + wave - 1) / wave));
     if (e.family == PK_FAMILY_MFMA) return dtype == PK_BF16 ? 2048.0 : 256.0;
     // VALU: 64 lanes x 4 SIMDs / 4 cycles = 64 multiply-adds per clock for
-    // float32; int32 multiplies run at a quarter of that.  The tiled kernel
+    // float32; int32 multiply-adds run at half of that (measured).  The tiled kernel
     // also reads 1 + s LDS words per s multiply-adds, which caps it near 24
     // multiply-adds per clock, rising slowly with s; the direct kernel is
     // bound by global/L1 reads (about one multiply-add per clock).
     const double s = std::max(1, e.s);
-    double mads = dtype == PK_I32 ? 16.0 : 64.0;
+    double mads = dtype == PK_I32 ? 32.0 : 64.0;
     if (!(e.variant & PK_VALU_NOLDS))
         mads = std::min(mads, 24.0 * std::pow(s / (1.0 + s), 0.25));
     else
