@@ -100,6 +100,7 @@ typedef struct {
  * (not a strategy of the case table; set only in instance descriptions) */
 #define PK_MFMA_SINGLE 1
 #define PK_MFMA_GROUPED 2
+#define PK_MFMA_ELEMENT 4 /* internal: the twin of a program that reads rows element by element */
 
 /* A leaf choice together with its program parameters E.
  *   family  - PK_FAMILY_*

@@ -32,6 +32,8 @@ enumeration over a grid of machines and the whole program-parameter domain:
   as the 1D Jacobi family; the cached program holds the tile's s' * B values
   of a and of b and the leading coefficient: 4 * (2 * s' * B + 1) bytes;
   threads B; 32-bit residues only (stored under the int32 dtype).
+* An MFMA program also exists as an element-load twin (rows not aligned for
+  16-byte loads); the program's registers are the larger of the two.
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -56,6 +58,7 @@ F32, I32, BF16 = 0, 1, 2
 VALU, MFMA, TRANSPOSE, MADD, JACOBI, POLYDIV = 0, 1, 2, 3, 4, 5
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
+ELEMENT = 4                 # MFMA: the twin instance reading rows element by element
 
 VALU_VARIANTS = (0, GRAN, GRAN | NOLDS, NOLDS)
 MFMA_VARIANTS = (0, SINGLE)
@@ -141,6 +144,10 @@ class InstanceData:
             e = self.by_key.get((family, dt, kernel, bx, by, outs))
         else:
             e = self.by_key.get((MFMA, dtype, variant & SINGLE) + tuple(point))
+            twin = self.by_key.get((MFMA, dtype, (variant & SINGLE) | ELEMENT) + tuple(point))
+            if e is not None and twin is not None and "vgpr" in e:
+                return max(regs_per_block(e["vgpr"], e["agpr"], e["threads"]),
+                           regs_per_block(twin["vgpr"], twin["agpr"], twin["threads"]))
         if e is None or "vgpr" not in e:
             return None
         return regs_per_block(e["vgpr"], e["agpr"], e["threads"])

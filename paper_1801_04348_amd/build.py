@@ -48,6 +48,7 @@ FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA, FAM_PD = 0, 1, 2, 3, 4, 5
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
+MFMA_ELEMENT = 4
 
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
@@ -103,6 +104,13 @@ def instances():
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
+                # the element-load twin, launched for rows not aligned for 16-byte
+                # loads (none for the largest bf16 tile, whose twin would spill)
+                if dt == BF16 and bm * bn >= 256 * 256:
+                    continue
+                body_el = "pkk::%s<%d, %d, %d, %d, %d, %d, false>(a);" % (fn, bm, bn, bk, wm, wn, stages)
+                entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT)
+                out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
     # transposition: tiled and direct programs (bit copies of 4-byte elements)
     for bx in TR_BX:
         for by in TR_BY:

@@ -112,7 +112,13 @@ bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb
     return aligned16(B) && ldb % 4 == 0;
 }
 
-int launch(const pk_machine &m, const KernelEntry &e, const MmArgs &args, hipStream_t stream) {
+int launch(const pk_machine &m, const KernelEntry &e0, const MmArgs &args, hipStream_t stream) {
+    const KernelEntry *pe = &e0;
+    if (e0.family == PK_FAMILY_MFMA && !args.vec) {  // rows not aligned: the element-load twin
+        pe = element_twin(e0);
+        if (!pe) return fail(PK_ERR_NOT_INSTANTIATED, std::string("no element-load twin of ") + e0.name);
+    }
+    const KernelEntry &e = *pe;
     const int64_t grid = grid_of(m, e, args.M, args.N);
     if (grid <= 0) return PK_OK;
     if (grid > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "grid too large");

@@ -117,7 +117,12 @@ int64_t table_regs(int family, int variant, int dtype, const std::vector<int64_t
     if (!e) return missing_table_value;
     const KernelResources *r = resources_of(e->name);
     if (!r) return missing_table_value;
-    return regs_per_block(*r, e->threads, wave);
+    int64_t v = regs_per_block(*r, e->threads, wave);
+    // an MFMA program runs as its element-load twin on unaligned rows: the
+    // program needs the larger of the two register allocations
+    if (const KernelEntry *t = element_twin(*e))
+        if (const KernelResources *rt = resources_of(t->name)) v = std::max(v, regs_per_block(*rt, t->threads, wave));
+    return v;
 }
 
 }  // namespace
@@ -390,6 +395,15 @@ const KernelEntry *find_polydiv_fused(int variant, int64_t bx, int64_t s) {
     const int v = variant & (PK_POLYDIV_FUSED | PK_POLYDIV_WIDE);
     for (const auto &e : registry())
         if (e.family == PK_FAMILY_POLYDIV && e.variant == v && e.bx == bx && e.s == s) return &e;
+    return nullptr;
+}
+
+const KernelEntry *element_twin(const KernelEntry &e) {
+    if (e.family != PK_FAMILY_MFMA || (e.variant & (PK_MFMA_GROUPED | PK_MFMA_ELEMENT))) return nullptr;
+    for (const auto &t : registry())
+        if (t.family == PK_FAMILY_MFMA && t.dtype == e.dtype && t.variant == (e.variant | PK_MFMA_ELEMENT) &&
+            t.bm == e.bm && t.bn == e.bn && t.bk == e.bk && t.wm == e.wm && t.wn == e.wn)
+            return &t;
     return nullptr;
 }
 

@@ -365,18 +365,20 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 }
 
 // ------------------------------------------------------------------ single product
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+// WIDE: 16-byte loads along aligned rows; the element-load twin (WIDE =
+// false) is a kernel of its own, so neither carries the other's load path.
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
 __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, a.vec != 0);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, WIDE);
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
 __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, a.vec != 0);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, WIDE);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)

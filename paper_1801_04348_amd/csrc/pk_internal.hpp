@@ -158,6 +158,10 @@ std::vector<int64_t> machine_values(const Family &fam, const pk_machine &m);
 bool variant_fits(const Family &fam, uint32_t variant, const std::vector<int64_t> &pt,
                   const std::vector<int64_t> &machine_vals);
 const KernelEntry *find_instance(int family, int variant, int dtype, const std::vector<int64_t> &pt);
+// The element-load twin of a single-launch MFMA instance (same program,
+// rows read element by element), or null.
+const KernelEntry *element_twin(const KernelEntry &e);
+
 // The one-launch polynomial-division instance named by a variant
 // (PK_POLYDIV_FUSED, with or without PK_POLYDIV_WIDE) and (bx, s), or null.
 const KernelEntry *find_polydiv_fused(int variant, int64_t bx, int64_t s);

@@ -164,7 +164,7 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
             c.leaf = leaf;
             c.variant = (int)part->solved.leaves[leaf].applied;
             c.entry = find_instance(family, c.variant, dtype, part->fam.points[i]);
-            if (!c.entry) continue;
+            if (!c.entry || (!wide && !element_twin(*c.entry))) continue;
             c.estimate = estimate_seconds(tbl->machine, *c.entry, dtype, M, N, K, wide);
             out.push_back(c);
         }

@@ -402,3 +402,27 @@ def test_case_pick_minimises_the_estimate():
             assert got == want, (dtype, M, N, K)
     with pytest.raises(pk.PkError):
         pk.pk_estimate(t, pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=32, by=8, s=1), "f32", 1, 1, 1)
+
+
+def test_every_mfma_program_has_an_element_load_twin(gfx_desc):
+    # the twin reads unaligned rows; the program's register symbol covers both
+    inst = {e["name"]: e for e in gfx_desc["instances"]}
+    single = [e for e in gfx_desc["instances"] if e["family"] == en.MFMA and not e["variant"] & (2 | en.ELEMENT)]
+    for e in single:
+        twin = inst.get(e["name"] + "_el")
+        if e["dtype"] == 2 and e["bm"] * e["bn"] >= 256 * 256:
+            assert twin is None
+            continue
+        assert twin is not None and twin["variant"] == e["variant"] | en.ELEMENT, e["name"]
+        assert twin["lds_bytes"] == e["lds_bytes"] and twin["scratch"] == 0
+    data = en.InstanceData(gfx_desc["instances"])
+    for part in gfx_desc["parts"]:
+        if part["family"] != en.MFMA:
+            continue
+        for sym, vals in part["tables"].items():
+            v = en.SINGLE if "one" in sym else 0
+            for pt, val in zip(part["points"], vals):
+                e = inst["pk_mfma_%s_%dx%dx%d_w%dx%d_st%d" % ({0: "f32", 2: "bf16"}[part["dtype"]], *pt,
+                                                             1 if v else 2)]
+                own = en.regs_per_block(e["vgpr"], e["agpr"], e["threads"])
+                assert val == data.regs(en.MFMA, part["dtype"], v, tuple(pt)) and val >= own

@@ -59,12 +59,15 @@ def test_traffic_scaled_by_the_copy(tmp_path):
     for counter, cdir, copy_val, kern_val in (("FETCH_SIZE", "f", copy_kib / 2, 100.0), ("WRITE_SIZE", "w", copy_kib, 40.0)):
         d = tmp_path / cdir
         d.mkdir()
-        names = ["copy"] * 3 + ["pk_k", "pk_k"] + ["copy"] + ["pk_k", "pk_k"] + ["copy"] + ["pk_k"]
+        copy = "void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctor_add<float> >"
+        # a runtime fill of a large buffer between the markers must not count as one
+        names = ([copy] * 3 + ["pk_k", "__amd_rocclr_fillBufferAligned", "pk_k"] + [copy] + ["pk_k", "pk_k"]
+                 + [copy] + ["pk_k"])
         with open(d / "x_counter_collection.csv", "w", newline="") as f:
             w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
             w.writeheader()
             for i, n in enumerate(names):
-                v = copy_val if n == "copy" else (kern_val if 6 <= i <= 7 else 999.0)
+                v = copy_val if n in (copy, "__amd_rocclr_fillBufferAligned") else (kern_val if 7 <= i <= 8 else 999.0)
                 w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": n, "Counter_Name": counter, "Counter_Value": v})
     out = tmp_path / "t.json"
     subprocess.run([sys.executable, os.path.join(ROOT, "paper_1801_04348_amd", "traffic.py"), "--fetch",
