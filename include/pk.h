@@ -374,20 +374,22 @@ int pk_instance_count(void);
 const char *pk_instance_name(int i);
 
 /* ------------------------------------------------------------------ cost model */
-/* The learned cost model: a 10-64-64-1 ReLU network predicting ln(seconds)
+/* The learned cost model: an 11-64-64-1 ReLU network predicting ln(seconds)
  * of a candidate launch from PK_NFEATURES features, trained on the device by
  * the library's own kernels (forward, backward, Adam) on timings from
  * pk_measure.  Not in the paper: it stands in for the auto-tuning the paper
  * leaves open for the program parameters (Section 1). */
-#define PK_NFEATURES 10
+#define PK_NFEATURES 11
 typedef struct pk_costmodel pk_costmodel; /* opaque */
 
 /* Features of candidate *p for C(MxN) = A(MxK) B(KxN) on the bound machine:
  * ln M, ln N, ln K, ln tile_m, ln tile_n, ln(outputs per work-item), LDS
  * bytes / 65536, estimated occupancy (resident wavefronts / maximum), tile
- * padding efficiency, wave quantisation efficiency.  out: PK_NFEATURES floats.
- * Errors as pk_launch_shape. */
-int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+ * padding efficiency, wave quantisation efficiency, and `wide` (1 when the
+ * operands' rows are aligned for the MFMA programs' 16-byte loads, 0 when they
+ * run as their element-load twins; see pk_matmul).  out: PK_NFEATURES
+ * floats.  Errors as pk_launch_shape. */
+int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 float *out);
 
 /* Trains a model on the table's device: X is n x PK_NFEATURES row-major

@@ -55,7 +55,10 @@ def fingerprint_of(pk, tbl):
 def feature_rows(pk, tbl, rec):
     import numpy as np
     M, N, K = rec["shape"]
-    X = np.stack([pk.pk_features(tbl, pk.params(**c["params"]), rec["dtype"], M, N, K) for c in rec["candidates"]])
+    # the tuner's operands are packed prefixes of 16-byte aligned buffers
+    wide = pk.packed_rows_wide(rec["dtype"], N, K)
+    X = np.stack([pk.pk_features(tbl, pk.params(**c["params"]), rec["dtype"], M, N, K, wide)
+                  for c in rec["candidates"]])
     t = np.array([c["seconds"] for c in rec["candidates"]], dtype=np.float64)
     return X, t
 

@@ -1,4 +1,4 @@
-// Learned cost model: a 10-64-64-1 ReLU network that predicts the logarithm
+// Learned cost model: an 11-64-64-1 ReLU network that predicts the logarithm
 // of a candidate's launch time from features of (candidate, M, N, K), trained
 // on the device by the kernels below on timings the exhaustive tuner records.
 // It replaces the analytic score when selecting among the case table's
@@ -257,7 +257,7 @@ std::string machine_fingerprint(const pk_machine &m) {
 //   7    estimated occupancy: resident wavefronts per CU / maximum
 //   8    tile padding efficiency: M N / (padded M) (padded N)
 //   9    wave quantisation efficiency: tiles / (rounds * resident slots)
-void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, float *f) {
+void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, float *f) {
     const int wave = m.wave > 0 ? m.wave : 64;
     const int64_t tm = (M + e.tile_m - 1) / e.tile_m, tn = (N + e.tile_n - 1) / e.tile_n;
     const int64_t tiles = tm * tn;
@@ -276,6 +276,7 @@ void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, i
     f[7] = (float)std::min(1.0, waves / waves_max);
     f[8] = (float)((double)M * N / ((double)tm * e.tile_m * (double)tn * e.tile_n));
     f[9] = (float)((double)tiles / ((double)rounds * slots));
+    f[10] = wide ? 1.0f : 0.0f;
 }
 
 // ln(seconds) predictions for rows of raw features, on `device`
@@ -305,14 +306,14 @@ using namespace pk;
 
 extern "C" {
 
-int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 float *out) {
     if (!tbl || !p || !out) return fail(PK_ERR_INVALID_ARG, "null argument");
     pk_params q;
     const KernelEntry *e = nullptr;
     int rc = resolve(tbl, p, (int)dtype, &q, &e);
     if (rc != PK_OK) return rc;
-    features(tbl->machine, *e, M, N, K, out);
+    features(tbl->machine, *e, M, N, K, wide != 0, out);
     return PK_OK;
 }
 

@@ -146,7 +146,7 @@ def lib():
         L.pk_kernel_name.argtypes = [vp, ctypes.POINTER(pk_params), i32]
         L.pk_kernel_name.restype = ctypes.c_char_p
         f32p = ctypes.POINTER(ctypes.c_float)
-        L.pk_features.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, f32p]
+        L.pk_features.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, i32, f32p]
         L.pk_costmodel_train.argtypes = [vp, f32p, f32p, i64, i32, ctypes.c_float, ctypes.c_uint64,
                                          ctypes.POINTER(vp), f32p]
         L.pk_costmodel_predict.argtypes = [vp, i32, f32p, i64, f32p]
@@ -410,7 +410,7 @@ def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=No
 
 
 # ---------------------------------------------------------------------- cost model
-PK_NFEATURES = 10
+PK_NFEATURES = 11
 
 
 def _fbuf(a):
@@ -419,12 +419,22 @@ def _fbuf(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
-def pk_features(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):
+def pk_features(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int, wide: bool = True):
+    """wide: the operands' rows are aligned for the MFMA programs' 16-byte
+    loads (packed operands: K and N multiples of 4 in f32, of 8 and 2 in bf16)."""
     import numpy as np
     out = np.zeros(PK_NFEATURES, dtype=np.float32)
-    _check(lib().pk_features(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K,
+    _check(lib().pk_features(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, 1 if wide else 0,
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return out
+
+
+def packed_rows_wide(dtype, N: int, K: int) -> bool:
+    """Whether packed operands (lda = K, ldb = N) from 16-byte aligned bases
+    have rows aligned for the MFMA programs' wide loads."""
+    if _dt(dtype) == PK_BF16:
+        return K % 8 == 0 and N % 2 == 0
+    return K % 4 == 0 and N % 4 == 0
 
 
 class CostModel:

@@ -67,8 +67,12 @@ def test_features_by_hand():
     rounds = math.ceil(tiles / slots)
     want = [math.log(M), math.log(N), math.log(K), math.log(128), math.log(128), math.log(128 * 128 / 256),
             inst["lds_bytes"] / 65536, min(1.0, occ * 4 / (m.max_threads_cu / 64)),
-            M * N / (math.ceil(M / 128) * 128 * math.ceil(N / 128) * 128), tiles / (rounds * slots)]
+            M * N / (math.ceil(M / 128) * 128 * math.ceil(N / 128) * 128), tiles / (rounds * slots), 1.0]
     assert np.allclose(f, want, rtol=1e-6), (f, want)
+    f0 = pk.pk_features(t, p, "f32", M, N, K, wide=False)
+    assert f0[10] == 0.0 and np.array_equal(f0[:10], f[:10])
+    assert pk.packed_rows_wide("f32", 3000, 512) and not pk.packed_rows_wide("f32", 3000, 513)
+    assert pk.packed_rows_wide("bf16", 3000, 512) and not pk.packed_rows_wide("bf16", 3001, 512)
 
 
 @pytest.mark.gpu
