@@ -394,7 +394,8 @@ int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t
 
 /* Trains a model on the table's device: X is n x PK_NFEATURES row-major
  * (host), seconds the n measured launch times (host, > 0).  Features and
- * ln(seconds) are standardised; parameters start He-uniform from `seed`;
+ * ln(seconds) are standardised; weights and biases start uniform on
+ * +-1/sqrt(fan-in) from `seed`;
  * `epochs` full-batch Adam steps (b1 0.9, b2 0.999, eps 1e-8) at rate lr on
  * the mean squared error.  *out is owned by the caller (pk_costmodel_free);
  * *final_loss (optional) is the loss in standardised units.

@@ -110,7 +110,9 @@ def instances():
                     continue
                 body_el = "pkk::%s<%d, %d, %d, %d, %d, %d, false>(a);" % (fn, bm, bn, bk, wm, wn, stages)
                 entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT)
-                out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
+                # (a translation unit of its own: compiled beside the wide kernel
+                # it changes the wide kernel's instruction schedule, measurably)
+                out.append(("mfma_%s_%d_el" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
     # transposition: tiled and direct programs (bit copies of 4-byte elements)
     for bx in TR_BX:
         for by in TR_BY:

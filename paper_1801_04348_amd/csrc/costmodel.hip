@@ -401,16 +401,20 @@ int pk_costmodel_train(const pk_table *tbl, const float *X, const float *seconds
         std::vector<float> Xs((size_t)n * IN);
         for (int64_t r = 0; r < n; ++r)
             for (int k = 0; k < IN; ++k) Xs[r * IN + k] = (X[r * IN + k] - cm->xmean[k]) / cm->xstd[k];
-        // He-uniform initialisation, zero biases
+        // weights and biases of a layer uniform on +-1/sqrt(fan-in): trained on
+        // the tuner's timings this reached a lower loss and regret than
+        // He-uniform weights with zero biases (which start with ~2.4x larger
+        // activations)
         cm->params.assign(NP, 0.0f);
         std::mt19937_64 rng(seed);
-        auto init = [&](int off, int rows, int cols) {
-            std::uniform_real_distribution<float> u(-std::sqrt(6.0f / cols), std::sqrt(6.0f / cols));
+        auto init = [&](int off, int boff, int rows, int cols) {
+            std::uniform_real_distribution<float> u(-1.0f / std::sqrt((float)cols), 1.0f / std::sqrt((float)cols));
             for (int i = 0; i < rows * cols; ++i) cm->params[off + i] = u(rng);
+            for (int i = 0; i < rows; ++i) cm->params[boff + i] = u(rng);
         };
-        init(OFF_W1, H, IN);
-        init(OFF_W2, H, H);
-        init(OFF_W3, 1, H);
+        init(OFF_W1, OFF_B1, H, IN);
+        init(OFF_W2, OFF_B2, H, H);
+        init(OFF_W3, OFF_B3, 1, H);
 
         CM_CHECK(hipSetDevice(tbl->device));
         DeviceBuffers d;
