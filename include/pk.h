@@ -120,7 +120,12 @@ typedef struct {
  * 1D Jacobi family: bx = work-items per workgroup (Fig. 6's B), s = points
  *   per work-item (s); by unused (0 or 1); strategy bits as the VALU family
  *   (PK_VALU_GRAN: s = 1, the second case; PK_VALU_NOLDS: no LDS caching,
- *   the third case).
+ *   the third case).  variant PK_JACOBI_FUSED (with leaf = -1) selects this
+ *   library's several-steps-per-launch program (bx in {256, 512, 1024}, s in
+ *   {1, 2, 4}): a launch advances an odd number of steps, up to 15, in LDS
+ *   with a recomputed halo, and the last step runs alone, so both halves end
+ *   as the per-step schedule leaves them; not part of the case table (its
+ *   resources are checked against the machine when it is chosen).
  * Polynomial-division family: bx = work-items per workgroup (Fig. 8's B),
  *   s = coefficients per work-item; by unused (0 or 1); strategy bits as the
  *   1D Jacobi family.  Its table is stored under PK_I32 (32-bit residues).
@@ -131,6 +136,7 @@ typedef struct {
  *   N - M <= 1024 and bx >= 64 and is not part of the case table (its
  *   resources are checked against the machine when it is chosen). */
 #define PK_POLYDIV_FUSED 4
+#define PK_JACOBI_FUSED 4
 #define PK_POLYDIV_WIDE 8 /* internal: the instance holding up to 1024 quotient coefficients */
 typedef struct {
     int32_t family;
@@ -325,7 +331,9 @@ int pk_select_madd(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, in
  * Errors as pk_transpose. */
 int pk_jacobi1d(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype, void *a, int64_t N,
                 int64_t steps, void *hip_stream);
-int pk_select_jacobi1d(const pk_table *tbl, pk_dtype dtype, int64_t N, int policy, pk_params *out);
+/* Chooses for `steps` time steps on vectors of N points (CASE or EXHAUSTIVE,
+ * among the case table's per-step programs and the several-steps program). */
+int pk_select_jacobi1d(const pk_table *tbl, pk_dtype dtype, int64_t N, int64_t steps, int policy, pk_params *out);
 
 /* ------------------------------------------------------------------ polynomial division */
 /* Division modulo a prime (Section 5, Fig. 8), in place on device arrays:

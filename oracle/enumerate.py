@@ -92,6 +92,8 @@ def transpose_lds(variant: int, bx: int, by: int, s: int) -> int:
 
 
 def jacobi_lds(variant: int, b: int, s: int) -> int:
+    if variant & 4:             # several steps per launch: two windows with a 16-point halo each side
+        return 8 * (s * b + 32)
     if variant & NOLDS:
         return 0
     outs = 1 if variant & GRAN else s

@@ -151,6 +151,15 @@ def instances():
                                  bm=0, bn=0, wm=0, wn=0, threads=b, lds=lds, tile_m=1, tile_n=s * b,
                                  args="pkk::JaArgs a")
                     out.append(("jacobi_%s" % DT_NAME[dt], name, body, entry))
+    # 1D Jacobi: several steps per launch (odd step counts, up to 15)
+    for dt in (F32, I32):
+        for b in (256, 512, 1024):
+            for s in (1, 2, 4):
+                name = "pk_jacobi_fused_%s_b%d_s%d" % (DT_NAME[dt], b, s)
+                body = "pkk::jacobi_fused<%s, %d, %d>(a);" % (DT_CTYPE[dt], b, s)
+                entry = dict(family=FAM_JA, variant=4, dtype=dt, bx=b, by=1, s=s, bk=0, bm=0, bn=0, wm=0, wn=0,
+                             threads=b, lds=2 * 4 * (s * b + 2 * 16), tile_m=1, tile_n=s * b, args="pkk::JfArgs a")
+                out.append(("jacobi_fused", name, body, entry))
     # polynomial division steps: cached (LDS) and direct programs, 32-bit residues
     for nolds in (False, True):
         for b in JA_B:

@@ -358,6 +358,11 @@ const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dty
         if (!e) fail(PK_ERR_NOT_INSTANTIATED, "no one-launch division instance for these parameters");
         return e ? e->name : nullptr;
     }
+    if (p->family == PK_FAMILY_JACOBI && p->variant >= 0 && (p->variant & PK_JACOBI_FUSED)) {
+        e = find_jacobi_fused((int)dtype, p->bx, p->s);
+        if (!e) fail(PK_ERR_NOT_INSTANTIATED, "no several-steps Jacobi instance for these parameters");
+        return e ? e->name : nullptr;
+    }
     if (resolve(tbl, p, (int)dtype, &q, &e) != PK_OK) return nullptr;
     return e->name;
 }

@@ -407,4 +407,11 @@ const KernelEntry *element_twin(const KernelEntry &e) {
     return nullptr;
 }
 
+const KernelEntry *find_jacobi_fused(int dtype, int64_t bx, int64_t s) {
+    for (const auto &e : registry())
+        if (e.family == PK_FAMILY_JACOBI && e.variant == PK_JACOBI_FUSED && e.dtype == dtype && e.bx == bx && e.s == s)
+            return &e;
+    return nullptr;
+}
+
 }  // namespace pk

@@ -86,3 +86,71 @@ __device__ __forceinline__ void jacobi_direct(const JaArgs &a) {
 }
 
 }  // namespace pkk
+
+namespace pkk {
+
+// Several time steps in one launch (a program of this library, not one of
+// the paper's): each workgroup stages its tile of S * B interior points with
+// a halo of k points on each side in LDS, advances the window k steps there
+// (the valid part shrinking by one point per side per step), and writes the
+// tile's points after k steps to the other half.  The end points are never
+// written, and each step reads those of the half it reads: the input half's
+// for odd steps of the launch, the output half's for even ones.  The arithmetic of every point and step is the
+// per-step kernels', so results are bit-identical; the halo is recomputed by
+// neighbouring workgroups instead of exchanged.  k is odd, 1 <= k <
+// kJaMaxSteps: after an odd number of steps the state belongs in the other
+// half, exactly where the per-step schedule would have put it.
+// LDS bytes: 2 * 4 * (S * B + 2 * kJaMaxSteps).
+constexpr int kJaMaxSteps = 16;
+
+struct JfArgs {
+    const void *in;
+    void *out;
+    int32_t N;  // points per half
+    int32_t k;  // steps this launch
+};
+
+template <typename T, int B, int S>
+__device__ __forceinline__ void jacobi_fused(const JfArgs &a) {
+    constexpr int TW = S * B, LW = TW + 2 * kJaMaxSteps;
+    __shared__ T buf[2][LW];
+    const T *__restrict__ in = static_cast<const T *>(a.in);
+    T *__restrict__ out = static_cast<T *>(a.out);
+    const int N = a.N, k = a.k, t = threadIdx.x;
+    const int n = N - 2, L = TW + 2 * k;
+    const T in0 = in[0], inN = in[N - 1], out0 = out[0], outN = out[N - 1];
+    const int tiles = (n + TW - 1) / TW;
+    for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
+        const int g0 = 1 + b * TW;  // first interior point of the tile
+        const int w0 = g0 - k;      // window start (may lie before the vector)
+        for (int i = t; i < L; i += B) {
+            const int g = w0 + i;
+            buf[0][i] = (g >= 0 && g < N) ? in[g] : T(0);
+        }
+        __syncthreads();
+        for (int j = 1; j <= k; ++j) {
+            const T *src = buf[(j - 1) & 1];
+            T *dst = buf[j & 1];
+            for (int i = j + t; i < L - j; i += B) {
+                const int g = w0 + i;
+                if (g == 0)
+                    dst[i] = (j & 1) ? out0 : in0;  // the ends of the half step j wrote
+                else if (g == N - 1)
+                    dst[i] = (j & 1) ? outN : inN;
+                else if (g < 0 || g >= N)
+                    dst[i] = src[i];  // outside the vector: never read by a valid point
+                else
+                    dst[i] = Avg3<T>::f(src[i - 1], src[i], src[i + 1]);
+            }
+            __syncthreads();
+        }
+        const T *res = buf[k & 1];
+        for (int o = t; o < TW; o += B) {
+            const int g = g0 + o;
+            if (g < N - 1) out[g] = res[k + o];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace pkk

@@ -162,6 +162,9 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
 // rows read element by element), or null.
 const KernelEntry *element_twin(const KernelEntry &e);
 
+// The several-steps 1D Jacobi instance of (dtype, bx, s), or null.
+const KernelEntry *find_jacobi_fused(int dtype, int64_t bx, int64_t s);
+
 // The one-launch polynomial-division instance named by a variant
 // (PK_POLYDIV_FUSED, with or without PK_POLYDIV_WIDE) and (bx, s), or null.
 const KernelEntry *find_polydiv_fused(int variant, int64_t bx, int64_t s);

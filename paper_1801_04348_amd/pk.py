@@ -38,6 +38,7 @@ PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_J
     0, 1, 2, 3, 4, 5)
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_POLYDIV_FUSED, PK_POLYDIV_WIDE = 4, 8
+PK_JACOBI_FUSED = 4
 PK_MFMA_SINGLE = 1
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
 
@@ -137,7 +138,7 @@ def lib():
         L.pk_select_madd.restype = i32
         L.pk_jacobi1d.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, i64, vp]
         L.pk_jacobi1d.restype = i32
-        L.pk_select_jacobi1d.argtypes = [vp, i32, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_jacobi1d.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(pk_params)]
         L.pk_select_jacobi1d.restype = i32
         L.pk_polydiv.argtypes = [vp, ctypes.POINTER(pk_params), vp, i64, vp, i64, ctypes.c_uint32, vp]
         L.pk_polydiv.restype = i32
@@ -319,9 +320,9 @@ def pk_madd(tbl: Table, p, dtype, A, B, C, stream=None):
                          b, max(ldb, N), c, max(ldc, N), M, N, _stream(stream)))
 
 
-def pk_select_jacobi1d(tbl: Table, dtype, N: int, policy: int = PK_POLICY_CASE) -> pk_params:
+def pk_select_jacobi1d(tbl: Table, dtype, N: int, policy: int = PK_POLICY_CASE, steps: int = 1) -> pk_params:
     out = pk_params()
-    _check(lib().pk_select_jacobi1d(tbl.handle, _dt(dtype), N, policy, ctypes.byref(out)))
+    _check(lib().pk_select_jacobi1d(tbl.handle, _dt(dtype), N, steps, policy, ctypes.byref(out)))
     return out
 
 

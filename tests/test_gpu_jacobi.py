@@ -94,7 +94,7 @@ def test_paper_length(table, policy):
     # Table 2: four time steps over a vector of length 2^15 + 2
     N = 2 ** 15 + 2
     for dt, a in zip(("i32", "f32"), arrays(N, 41)):
-        p = pk.pk_select_jacobi1d(table, dt, N, policy)
+        p = pk.pk_select_jacobi1d(table, dt, N, policy, steps=4)
         say("jacobi %s N=2^15+2 policy %d pick" % (dt, policy), p)
         got = run(table, p, dt, a, 4)
         assert np.array_equal(got.view(np.int32), oj.jacobi1d(a, 4, dt).view(np.int32))
@@ -103,7 +103,37 @@ def test_paper_length(table, policy):
 def test_large_length_whole(table):
     N = 2 ** 26 + 2
     a = inputs.full_range_i32((2 * N,), seed=51)
-    p = pk.pk_select_jacobi1d(table, "i32", N)
+    p = pk.pk_select_jacobi1d(table, "i32", N, steps=5)
     say("jacobi i32 N=2^26+2 pick", p)
     got = run(table, p, "i32", a, 5)
     assert np.array_equal(got, oj.jacobi1d(a, 5, "i32"))
+
+
+def fused(b, s):
+    return pk.params(family=pk.PK_FAMILY_JACOBI, leaf=-1, variant=pk.PK_JACOBI_FUSED, bx=b, s=s)
+
+
+@pytest.mark.parametrize("b", [256, 512, 1024])
+def test_several_steps_program(table, b):
+    # odd step counts per launch in LDS with a recomputed halo, the last step
+    # alone: both halves end as the per-step schedule leaves them, bit for bit
+    # (the halves' end points differ, so a step reading the wrong half's ends
+    # would show)
+    for N in (3001, 2, 3, 4, 17, 300):
+        for dt, a in zip(("i32", "f32"), arrays(N, N + b)):
+            for s in (1, 2, 4):
+                for T in (0, 1, 2, 3, 4, 5, 16, 17, 31):
+                    say("jacobi fused %s N=%d B=%d s=%d T=%d" % (dt, N, b, s, T))
+                    got = run(table, fused(b, s), dt, a, T)
+                    assert np.array_equal(got.view(np.int32), oj.jacobi1d(a, T, dt).view(np.int32)), (N, s, T)
+
+
+def test_several_steps_selection_and_refusal(table):
+    N = 2 ** 20 + 2
+    a = arrays(N, 61)[0]
+    for policy in (pk.PK_POLICY_CASE, pk.PK_POLICY_EXHAUSTIVE):
+        p = pk.pk_select_jacobi1d(table, "i32", N, policy, steps=4)
+        say("jacobi N=2^20+2 4 steps policy %d pick" % policy, p, pk.pk_kernel_name(table, p, "i32"))
+        assert np.array_equal(run(table, p, "i32", a, 4), oj.jacobi1d(a, 4, "i32"))
+    with pytest.raises(pk.PkError):                       # no instance at this point
+        run(table, fused(64, 1), "i32", a, 4)
