@@ -354,9 +354,11 @@ int pk_select_polydiv(const pk_table *tbl, int64_t N, int64_t M, int policy, pk_
 
 /* The CASE policy's analytic time estimate, in seconds, of one launch of a
  * choice (params resolved as in pk_matmul) for an M x N x K product: the
- * score pk_select's CASE policy minimises over the feasible set.  Matmul
- * families only.  Errors as pk_launch_shape. */
-int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+ * score pk_select's CASE policy minimises over the feasible set.  `wide`: the
+ * operands' rows are aligned for the MFMA programs' 16-byte loads (0: they
+ * run as their element-load twins, see pk_matmul).  Matmul families only.
+ * Errors as pk_launch_shape. */
+int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 double *seconds);
 
 /* Measured vector-ALU ceiling of the table's device, in operations per

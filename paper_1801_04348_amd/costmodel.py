@@ -131,7 +131,8 @@ def main():
         learned.append(best / t[pick])
         # CASE among the candidates the store holds (those feasible for the
         # operands' alignment), as pk_matmul's own CASE choice would be
-        est = [pk.pk_estimate(tbl, pk.params(**c["params"]), r["dtype"], M, N, K) for c in r["candidates"]]
+        wide = pk.packed_rows_wide(r["dtype"], N, K)
+        est = [pk.pk_estimate(tbl, pk.params(**c["params"]), r["dtype"], M, N, K, wide) for c in r["candidates"]]
         case.append(best / t[int(np.argmin(est))])
     out = {"learned": stats(learned), "learned_without_measurement": stats(model_only), "case": stats(case),
            "fallback_rate": fallbacks / len(recs), "candidates_measured_per_fallback": measured / max(fallbacks, 1),

@@ -367,7 +367,7 @@ const char *pk_kernel_name(const pk_table *tbl, const pk_params *p, pk_dtype dty
     return e->name;
 }
 
-int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K,
+int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 double *seconds) {
     if (!tbl || !p || !seconds) return fail(PK_ERR_INVALID_ARG, "null argument");
     if (M < 0 || N < 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "negative dimension");
@@ -377,7 +377,7 @@ int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t
     const KernelEntry *e = nullptr;
     int rc = resolve(tbl, p, (int)dtype, &q, &e);
     if (rc != PK_OK) return rc;
-    *seconds = estimate_seconds(tbl->machine, *e, (int)dtype, M, N, K);
+    *seconds = estimate_seconds(tbl->machine, *e, (int)dtype, M, N, K, wide != 0);
     return PK_OK;
 }
 

@@ -130,7 +130,8 @@ def lib():
         L.pk_select_transpose.restype = i32
         L.pk_probe_valu_rate.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.pk_probe_valu_rate.restype = i32
-        L.pk_estimate.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, ctypes.POINTER(ctypes.c_double)]
+        L.pk_estimate.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64, i32,
+                                  ctypes.POINTER(ctypes.c_double)]
         L.pk_estimate.restype = i32
         L.pk_madd.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, vp, i64, i64, i64, vp]
         L.pk_madd.restype = i32
@@ -366,10 +367,10 @@ def pk_probe_valu_rate(tbl: Table, dtype) -> float:
     return out.value
 
 
-def pk_estimate(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int) -> float:
+def pk_estimate(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int, wide: bool = True) -> float:
     """The CASE policy's analytic seconds for one launch of p on M x N x K."""
     out = ctypes.c_double()
-    _check(lib().pk_estimate(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, ctypes.byref(out)))
+    _check(lib().pk_estimate(tbl.handle, ctypes.byref(p), _dt(dtype), M, N, K, 1 if wide else 0, ctypes.byref(out)))
     return out.value
 
 
