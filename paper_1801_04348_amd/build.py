@@ -103,6 +103,11 @@ def instances():
                 entry = dict(family=FAM_MFMA, variant=0 if stages == 2 else MFMA_SINGLE, dtype=dt,
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
+                if dt == F32 and stages == 1 and wm * wn == 8:
+                    # at most 128 registers a lane, so that 512 work-items fit a
+                    # block register budget of 65536 (the smaller figure some
+                    # HIP runtimes report); this program does not spill there
+                    entry["attrs"] = "__attribute__((amdgpu_waves_per_eu(4)))"
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
                 # the element-load twin, launched for rows not aligned for 16-byte
                 # loads (none for the largest bf16 tile, whose twin would spill)
@@ -216,8 +221,9 @@ def generate():
                  '#include "kernels/jacobi.hpp"', '#include "kernels/polydiv.hpp"', ""]
         for name, body, entry in items:
             arg = entry.get("args", "pkk::MmArgs a")
-            lines.append('extern "C" __global__ void __launch_bounds__(%d) %s(%s) { %s }'
-                         % (entry["threads"], name, arg, body))
+            attrs = entry.get("attrs", "")
+            lines.append('extern "C" __global__ void __launch_bounds__(%d) %s%s(%s) { %s }'
+                         % (entry["threads"], attrs + " " if attrs else "", name, arg, body))
         lines.append("")
         lines.append("static const pkk::KernelEntry entries[] = {")
         for name, body, entry in items:

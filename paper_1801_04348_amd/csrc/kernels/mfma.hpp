@@ -105,6 +105,23 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
     f32x4 ra[A4], rb[B4];
+    // a K step that lies wholly inside aligned operands: no guards, so the
+    // loads issue back to back (guarded loads branch per load, and the
+    // compiler then waits for each load before the next)
+    auto gload_fast = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < A4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+            ra[u] = *reinterpret_cast<const f32x4 *>(A + (int64_t)(row0 + rr) * a.lda + k0 + c4);
+        }
+#pragma unroll
+        for (int u = 0; u < B4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+            rb[u] = *reinterpret_cast<const f32x4 *>(B + (int64_t)(k0 + rr) * a.ldb + col0 + c4);
+        }
+    };
     auto gload = [&](int k0) {
         const bool kfull = (k0 + BK <= K);
 #pragma unroll
@@ -172,13 +189,29 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
     };
 
     const int KT = (K + BK - 1) / BK;
+    // leading K steps that need no guards: all of them for an interior tile
+    // on aligned rows, except a partial last one
+    const int KF = (vec && interior) ? K / BK : 0;
     if (STAGES == 2) {
         if (KT > 0) {
-            gload(0);
+            if (KF > 0)
+                gload_fast(0);
+            else
+                gload(0);
             sstore(0);
         }
         __syncthreads();
-        for (int kt = 0; kt < KT; ++kt) {
+        int kt = 0;
+        // steps whose successor is unguarded too: a loop without branches, so
+        // the next step's loads stay in flight while this step multiplies
+        for (; kt + 1 < KF; ++kt) {
+            const int cur = kt & 1;
+            gload_fast((kt + 1) * BK);
+            compute(cur);
+            sstore(cur ^ 1);
+            __syncthreads();
+        }
+        for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
             compute(cur);
@@ -186,7 +219,15 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             __syncthreads();
         }
     } else {
-        for (int kt = 0; kt < KT; ++kt) {
+        int kt = 0;
+        for (; kt < KF; ++kt) {
+            gload_fast(kt * BK);
+            __syncthreads();
+            sstore(0);
+            __syncthreads();
+            compute(0);
+        }
+        for (; kt < KT; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
@@ -251,6 +292,22 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 
     u16x8 ra[A8];
     unsigned int rb[B8][8];  // 8 k rows of a column pair (n, n+1)
+    auto gload_fast = [&](int k0) {  // unguarded, as in the float32 tile
+#pragma unroll
+        for (int u = 0; u < A8; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+            ra[u] = *reinterpret_cast<const u16x8 *>(A + (int64_t)(row0 + rr) * a.lda + k0 + c8);
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int f = tid + u * NT;
+            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                rb[u][e] = *reinterpret_cast<const unsigned int *>(B + (int64_t)(k0 + kr + e) * a.ldb + col0 + cp);
+        }
+    };
     auto gload = [&](int k0) {
         const bool kfull = (k0 + BK <= K);
 #pragma unroll
@@ -325,13 +382,29 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
     };
 
     const int KT = (K + BK - 1) / BK;
+    // leading K steps that need no guards: all of them for an interior tile
+    // on aligned rows, except a partial last one
+    const int KF = (vec && interior) ? K / BK : 0;
     if (STAGES == 2) {
         if (KT > 0) {
-            gload(0);
+            if (KF > 0)
+                gload_fast(0);
+            else
+                gload(0);
             sstore(0);
         }
         __syncthreads();
-        for (int kt = 0; kt < KT; ++kt) {
+        int kt = 0;
+        // steps whose successor is unguarded too: a loop without branches, so
+        // the next step's loads stay in flight while this step multiplies
+        for (; kt + 1 < KF; ++kt) {
+            const int cur = kt & 1;
+            gload_fast((kt + 1) * BK);
+            compute(cur);
+            sstore(cur ^ 1);
+            __syncthreads();
+        }
+        for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
             compute(cur);
@@ -339,7 +412,15 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             __syncthreads();
         }
     } else {
-        for (int kt = 0; kt < KT; ++kt) {
+        int kt = 0;
+        for (; kt < KF; ++kt) {
+            gload_fast(kt * BK);
+            __syncthreads();
+            sstore(0);
+            __syncthreads();
+            compute(0);
+        }
+        for (; kt < KT; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
