@@ -71,6 +71,18 @@ def valu_lds(bx, by, s, nolds):
     return 0 if nolds else 4 * (by * (by + 1) + by * bx * s)
 
 
+def mfma_reg_cap(dt, threads, stages, kind):
+    """At most 65536 / threads registers a lane, so that the workgroup fits a
+    block register budget of 65536 (the smaller figure HIP runtimes report for
+    gfx950), where the compiler's own choice would exceed it and the capped
+    program compiles without spilling: element-load twins and grouped programs
+    of 256 work-items (256 registers; their loads at chosen addresses hold
+    more), and single-stage float32 programs of 512 (128)."""
+    if (dt == F32 and threads == 512 and stages == 1) or (kind != "wide" and threads == 256):
+        return "__attribute__((amdgpu_waves_per_eu(%d)))" % (threads // 128)
+    return ""
+
+
 def mfma_lds(dtype, bm, bn, bk, stages):
     if dtype == F32:
         return stages * 4 * (bm * (bk + 4) + bk * (bn + 4))
@@ -103,18 +115,15 @@ def instances():
                 entry = dict(family=FAM_MFMA, variant=0 if stages == 2 else MFMA_SINGLE, dtype=dt,
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
-                if dt == F32 and stages == 1 and wm * wn == 8:
-                    # at most 128 registers a lane, so that 512 work-items fit a
-                    # block register budget of 65536 (the smaller figure some
-                    # HIP runtimes report); this program does not spill there
-                    entry["attrs"] = "__attribute__((amdgpu_waves_per_eu(4)))"
+                entry["attrs"] = mfma_reg_cap(dt, 64 * wm * wn, stages, "wide")
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
                 # the element-load twin, launched for rows not aligned for 16-byte
                 # loads (none for the largest bf16 tile, whose twin would spill)
                 if dt == BF16 and bm * bn >= 256 * 256:
                     continue
                 body_el = "pkk::%s<%d, %d, %d, %d, %d, %d, false>(a);" % (fn, bm, bn, bk, wm, wn, stages)
-                entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT)
+                entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT,
+                                attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "twin"))
                 # (a translation unit of its own: compiled beside the wide kernel
                 # it changes the wide kernel's instruction schedule, measurably)
                 out.append(("mfma_%s_%d_el" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
@@ -197,7 +206,8 @@ def instances():
                 body = "pkk::%s<%d, %d, %d, %d, %d, %d>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages)
                 entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE),
                              dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
-                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, args="pkk::GroupArgs g")
+                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
+                             attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "grouped"))
                 out.append(("grouped_%s" % DT_NAME[dt], name, body, entry))
     return out
 

@@ -24,8 +24,11 @@
 //
 // Global loads are 16 bytes wide, so the leading dimensions must keep rows
 // 16-byte aligned (lda, ldb multiples of 4 floats / 8 bfloat16 and 16-byte
-// aligned bases); the host checks this.  Tiles crossing the matrix edge use
-// guarded element loads with zero fill and guarded stores.
+// aligned bases); the host checks this.  Tiles crossing the matrix edge clamp
+// the rows of A and the columns of B they read to the last one in range
+// (results outside C are never stored), read k beyond K from a block of zeros,
+// and guard their stores.  Edge loads choose an address, never a loaded value,
+// so they carry no branches and stay in flight together.
 //
 // Workgroup -> tile map: workgroups are dispatched round-robin over the 8 XCDs
 // (each with its own L2); blocks b and b+8 land on the same XCD, so the map
@@ -46,6 +49,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Pointers into global memory.  The grouped kernels read operand pointers
+// from descriptors in memory, where the compiler cannot infer the address
+// space and would emit flat accesses (which also wait on the LDS counter).
+template <class T> using gptr = const __attribute__((address_space(1))) T *;
+template <class T> using gmut = __attribute__((address_space(1))) T *;
+
+// the source of every element at k >= K (read only)
+static __device__ __attribute__((aligned(16))) unsigned int kZeroBlock[4] = {0u, 0u, 0u, 0u};
 
 constexpr int XCDS = 8;
 constexpr int GROUP_M = 8;
@@ -69,7 +81,7 @@ __device__ __forceinline__ void tile_of(int64_t b, int tiles_m, int tiles_n, int
 // One BM x BN output tile at (row0, col0).  `vec`: the rows of A and B are
 // 16-byte aligned, so interior tiles may use 16-byte loads.  The caller
 // synchronises the workgroup before reusing the LDS for another tile.
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
 __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -85,9 +97,9 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
     __shared__ __attribute__((aligned(16))) float As[STAGES][BM * LDA_S];
     __shared__ __attribute__((aligned(16))) float Bs[STAGES][BK * LDB_S];
 
-    const float *__restrict__ A = static_cast<const float *>(a.A);
-    const float *__restrict__ B = static_cast<const float *>(a.B);
-    float *__restrict__ C = static_cast<float *>(a.C);
+    const gptr<float> __restrict__ A = (gptr<float>)a.A;
+    const gptr<float> __restrict__ B = (gptr<float>)a.B;
+    const gmut<float> __restrict__ C = (gmut<float>)a.C;
     const int M = a.M, N = a.N, K = a.K;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -113,41 +125,89 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         for (int u = 0; u < A4; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
-            ra[u] = *reinterpret_cast<const f32x4 *>(A + (int64_t)(row0 + rr) * a.lda + k0 + c4);
+            ra[u] = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)(row0 + rr) * a.lda + k0 + c4);
         }
 #pragma unroll
         for (int u = 0; u < B4; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
-            rb[u] = *reinterpret_cast<const f32x4 *>(B + (int64_t)(k0 + rr) * a.ldb + col0 + c4);
+            rb[u] = *reinterpret_cast<gptr<f32x4>>(B + (int64_t)(k0 + rr) * a.ldb + col0 + c4);
         }
     };
+    // Any K step, edge tiles included.  EDGE_ADDR: every load goes to a chosen
+    // address (the wide/narrow choices are uniform across the workgroup), for
+    // programs whose steps are mostly edge steps (element loads, many small
+    // products); otherwise guarded loads, which hold fewer registers where
+    // edge steps are rare.
     auto gload = [&](int k0) {
-        const bool kfull = (k0 + BK <= K);
+        if constexpr (!EDGE_ADDR) {
+            const bool kfull = (k0 + BK <= K);
 #pragma unroll
-        for (int u = 0; u < A4; ++u) {
-            const int f = tid + u * NT;
-            const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
-            const int gr = row0 + rr, gc = k0 + c4;
-            if (vec && kfull && (interior || gr < M)) {
-                ra[u] = *reinterpret_cast<const f32x4 *>(A + (int64_t)gr * a.lda + gc);
-            } else {
+            for (int u = 0; u < A4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+                const int gr = row0 + rr, gc = k0 + c4;
+                if (vec && kfull && gr < M) {
+                    ra[u] = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)gr * a.lda + gc);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : 0.0f;
+                    for (int e = 0; e < 4; ++e)
+                        ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+                const int gr = k0 + rr, gc = col0 + c4;
+                if (vec && gr < K && gc + 4 <= N) {
+                    rb[u] = *reinterpret_cast<gptr<f32x4>>(B + (int64_t)gr * a.ldb + gc);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rb[u][e] = (gr < K && gc + e < N) ? B[(int64_t)gr * a.ldb + gc + e] : 0.0f;
+                }
+            }
+            return;
+        }
+        const gptr<float> zero = (gptr<float>)(const void *)kZeroBlock;
+        if (vec && k0 + BK <= K) {
+#pragma unroll
+            for (int u = 0; u < A4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+                ra[u] = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c4);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < A4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+                const gptr<float> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = k0 + c4 + e;
+                    ra[u][e] = *(k < K ? row + k : zero);
+                }
             }
         }
+        if (vec && col0 + BN <= N) {
 #pragma unroll
-        for (int u = 0; u < B4; ++u) {
-            const int f = tid + u * NT;
-            const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
-            const int gr = k0 + rr, gc = col0 + c4;
-            if (vec && gr < K && (interior || gc + 4 <= N)) {
-                rb[u] = *reinterpret_cast<const f32x4 *>(B + (int64_t)gr * a.ldb + gc);
-            } else {
+            for (int u = 0; u < B4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+                const int k = k0 + rr;
+                rb[u] = *reinterpret_cast<gptr<f32x4>>(k < K ? B + (int64_t)k * a.ldb + col0 + c4 : zero);
+            }
+        } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    rb[u][e] = (gr < K && gc + e < N) ? B[(int64_t)gr * a.ldb + gc + e] : 0.0f;
+            for (int u = 0; u < B4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+                const int k = k0 + rr;
+                const gptr<float> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) rb[u][e] = *(row ? row + min(col0 + c4 + e, N - 1) : zero);
             }
         }
     };
@@ -246,7 +306,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             for (int v = 0; v < 16; ++v) {
                 const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
                 if (interior || (gr < M && gc < N)) {
-                    float *p = C + (int64_t)gr * a.ldc + gc;
+                    const gmut<float> p = C + (int64_t)gr * a.ldc + gc;
                     *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
                 }
             }
@@ -255,7 +315,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
 
 // ------------------------------------------------------------------ bfloat16
 // bfloat16 tile; `vec`: A rows 16-byte aligned and B rows 4-byte aligned.
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
 __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -271,9 +331,9 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
     __shared__ __attribute__((aligned(16))) unsigned short As[STAGES][BM * LD_S];
     __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES][BN * LD_S];
 
-    const unsigned short *__restrict__ A = static_cast<const unsigned short *>(a.A);
-    const unsigned short *__restrict__ B = static_cast<const unsigned short *>(a.B);
-    float *__restrict__ C = static_cast<float *>(a.C);
+    const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A;
+    const gptr<unsigned short> __restrict__ B = (gptr<unsigned short>)a.B;
+    const gmut<float> __restrict__ C = (gmut<float>)a.C;
     const int M = a.M, N = a.N, K = a.K;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -297,7 +357,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         for (int u = 0; u < A8; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
-            ra[u] = *reinterpret_cast<const u16x8 *>(A + (int64_t)(row0 + rr) * a.lda + k0 + c8);
+            ra[u] = *reinterpret_cast<gptr<u16x8>>(A + (int64_t)(row0 + rr) * a.lda + k0 + c8);
         }
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
@@ -305,37 +365,89 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                rb[u][e] = *reinterpret_cast<const unsigned int *>(B + (int64_t)(k0 + kr + e) * a.ldb + col0 + cp);
+                rb[u][e] = *reinterpret_cast<gptr<unsigned int>>(B + (int64_t)(k0 + kr + e) * a.ldb + col0 + cp);
         }
     };
-    auto gload = [&](int k0) {
-        const bool kfull = (k0 + BK <= K);
+    auto gload = [&](int k0) {  // any K step: as in the float32 tile
+        if constexpr (!EDGE_ADDR) {
+            const bool kfull = (k0 + BK <= K);
 #pragma unroll
-        for (int u = 0; u < A8; ++u) {
-            const int f = tid + u * NT;
-            const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
-            const int gr = row0 + rr, gc = k0 + c8;
-            if (vec && kfull && (interior || gr < M)) {
-                ra[u] = *reinterpret_cast<const u16x8 *>(A + (int64_t)gr * a.lda + gc);
-            } else {
+            for (int u = 0; u < A8; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+                const int gr = row0 + rr, gc = k0 + c8;
+                if (vec && kfull && gr < M) {
+                    ra[u] = *reinterpret_cast<gptr<u16x8>>(A + (int64_t)gr * a.lda + gc);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : (unsigned short)0;
+                    for (int e = 0; e < 8; ++e)
+                        ra[u][e] = (gr < M && gc + e < K) ? A[(int64_t)gr * a.lda + gc + e] : (unsigned short)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B8; ++u) {
+                const int f = tid + u * NT;
+                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
+                const int gc = col0 + cp;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int gr = k0 + kr + e;
+                    if (vec && gr < K && gc + 2 <= N) {
+                        rb[u][e] = *reinterpret_cast<gptr<unsigned int>>(B + (int64_t)gr * a.ldb + gc);
+                    } else {
+                        const unsigned int lo = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : 0u;
+                        const unsigned int hi = (gr < K && gc + 1 < N) ? B[(int64_t)gr * a.ldb + gc + 1] : 0u;
+                        rb[u][e] = lo | (hi << 16);
+                    }
+                }
+            }
+            return;
+        }
+        if (vec && k0 + BK <= K) {
+#pragma unroll
+            for (int u = 0; u < A8; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+                ra[u] = *reinterpret_cast<gptr<u16x8>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c8);
+            }
+        } else {
+            const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
+#pragma unroll
+            for (int u = 0; u < A8; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+                const gptr<unsigned short> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + c8 + e;
+                    ra[u][e] = *(k < K ? row + k : zero);
+                }
             }
         }
+        if (vec && col0 + BN <= N) {
 #pragma unroll
-        for (int u = 0; u < B8; ++u) {
-            const int f = tid + u * NT;
-            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;  // column pair, first k row
-            const int gc = col0 + cp;
+            for (int u = 0; u < B8; ++u) {
+                const int f = tid + u * NT;
+                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;  // column pair, first k row
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int gr = k0 + kr + e;
-                if (vec && gr < K && (interior || gc + 2 <= N)) {
-                    rb[u][e] = *reinterpret_cast<const unsigned int *>(B + (int64_t)gr * a.ldb + gc);
-                } else {
-                    unsigned int lo = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : 0u;
-                    unsigned int hi = (gr < K && gc + 1 < N) ? B[(int64_t)gr * a.ldb + gc + 1] : 0u;
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + kr + e;
+                    rb[u][e] = *(k < K ? reinterpret_cast<gptr<unsigned int>>(B + (int64_t)k * a.ldb + col0 + cp)
+                                       : (gptr<unsigned int>)(const void *)kZeroBlock);
+                }
+            }
+        } else {
+            const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
+#pragma unroll
+            for (int u = 0; u < B8; ++u) {
+                const int f = tid + u * NT;
+                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
+                const int c0 = min(col0 + cp, N - 1), c1 = min(col0 + cp + 1, N - 1);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int k = k0 + kr + e;
+                    const gptr<unsigned short> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
+                    const unsigned int lo = *(row ? row + c0 : zero), hi = *(row ? row + c1 : zero);
                     rb[u][e] = lo | (hi << 16);
                 }
             }
@@ -438,7 +550,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             for (int v = 0; v < 16; ++v) {
                 const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
                 if (interior || (gr < M && gc < N)) {
-                    float *p = C + (int64_t)gr * a.ldc + gc;
+                    const gmut<float> p = C + (int64_t)gr * a.ldc + gc;
                     *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
                 }
             }
@@ -448,18 +560,20 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 // ------------------------------------------------------------------ single product
 // WIDE: 16-byte loads along aligned rows; the element-load twin (WIDE =
 // false) is a kernel of its own, so neither carries the other's load path.
+// The twins of workgroups up to 256 work-items load at chosen addresses (all
+// their steps take the edge path).
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
 __device__ __forceinline__ void mfma_f32(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, WIDE);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
 __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
     int tm, tn;
     tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, WIDE);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
@@ -474,7 +588,7 @@ __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
-        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
+        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0);
     }
 }
 
@@ -486,7 +600,7 @@ __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
-        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES>(a, tm * BM, tn * BN, d.vec != 0);
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0);
     }
 }
 
