@@ -114,10 +114,15 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
         return e0.elapsed_time(e1) / reps * 1e-3
 
     plan = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=policy)
-    n_launch, tiles, _ = plan.info()
+    n_launch, tiles, chosen = plan.info()
     plan.capture()
     t_graph = timed(lambda: plan.replay())
     t_plan = timed(lambda: plan.run())
+    # the program chosen by timing each candidate plan on these operands
+    plan_x = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=pk.PK_POLICY_EXHAUSTIVE)
+    chosen_x = plan_x.info()[2]
+    plan_x.capture()
+    t_graph_x = timed(lambda: plan_x.replay())
     picks = [pk.pk_select(tbl, dtype, int(M), int(N), int(K), pk.PK_POLICY_CASE) for (M, N, K) in dims]
 
     def loop():
@@ -135,7 +140,11 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
         loop()
     t_loop_graph = timed(lambda: graph.replay())
     return {"products": G, "gflop": round(flops / 1e9, 2), "launches": n_launch, "tiles": tiles,
+            "program": pk.pk_kernel_name(tbl, chosen[0], dtype),
             "grouped_graph_gflops": round(flops / t_graph / 1e9, 1),
+            "exhaustive_program": pk.pk_kernel_name(tbl, chosen_x[0], dtype),
+            "exhaustive_graph_gflops": round(flops / t_graph_x / 1e9, 1),
+            "exhaustive_pct_summed_roofline": round(roof / t_graph_x, 4),
             "grouped_gflops": round(flops / t_plan / 1e9, 1),
             "loop_gflops": round(flops / t_loop / 1e9, 1),
             "loop_graph_gflops": round(flops / t_loop_graph / 1e9, 1),

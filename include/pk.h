@@ -257,9 +257,12 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
  * instances that fit every product, the one whose tiles cost the least
  * compute-unit time summed over the products under the CASE policy's model
  * (one launch; the latency of a single product does not count when the
- * products run side by side).  `policy` is PK_POLICY_CASE or
- * PK_POLICY_LEARNED; both make that choice.  Rows that are not aligned for the 16-byte loads are read with
- * element loads.  The plan copies its descriptors to the device when created
+ * products run side by side).  `policy` PK_POLICY_CASE or PK_POLICY_LEARNED
+ * makes that choice; PK_POLICY_EXHAUSTIVE instead builds a plan of each
+ * program that fits every product, times it on the device (one untimed run,
+ * median of three) and keeps the fastest -- those runs write C, so it is
+ * refused (PK_ERR_INVALID_ARG) together with accumulate.  Rows that are not
+ * aligned for the 16-byte loads are read with element loads.  The plan copies its descriptors to the device when created
  * (allocating and synchronizing then); running it allocates nothing and does
  * not synchronize, so it may be captured in a HIP graph.  Pointers must stay
  * valid while the plan is used.  Errors: PK_ERR_INVALID_ARG,

@@ -3,7 +3,8 @@
 // A plan fixes, once, everything a grouped launch needs: for every product its
 // leaf and program parameters (given per product, or else one program for
 // all of them: among the MFMA points with grouped instances that fit every
-// product, the one whose tiles cost the least compute-unit time in total),
+// product, the one whose tiles cost the least compute-unit time in total, or
+// under EXHAUSTIVE the one whose plan runs fastest when timed),
 // its descriptor
 // (pointers, leading dimensions, sizes, whether rows are aligned for the wide
 // loads, first global tile index), and a tile -> product map.  Products are
@@ -17,6 +18,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 
 #include "pk_internal.hpp"
@@ -67,6 +69,38 @@ static bool aligned_rows(int dtype, const void *A, int64_t lda, const void *B, i
 
 using namespace pk;
 
+extern "C" int pk_grouped_plan_run(const pk_grouped_plan *plan, void *hip_stream);
+
+namespace pk {
+// seconds per run of a plan: one untimed run, then the median of three
+static int time_plan(const pk_grouped_plan *plan, double *secs) {
+    hipError_t err = hipSetDevice(plan->device);
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (err == hipSuccess) err = hipStreamCreate(&s);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    int rc = err == hipSuccess ? pk_grouped_plan_run(plan, s) : PK_ERR_HIP;
+    float t[3] = {0.f, 0.f, 0.f};
+    for (int i = 0; i < 3 && rc == PK_OK && err == hipSuccess; ++i) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess) rc = pk_grouped_plan_run(plan, s);
+        if (err == hipSuccess && rc == PK_OK) err = hipEventRecord(e1, s);
+        if (err == hipSuccess && rc == PK_OK) err = hipEventSynchronize(e1);
+        if (err == hipSuccess && rc == PK_OK) err = hipEventElapsedTime(&t[i], e0, e1);
+    }
+    if (s) hipStreamSynchronize(s);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (s) hipStreamDestroy(s);
+    if (rc != PK_OK) return rc;
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("timing a grouped plan: ") + hipGetErrorString(err));
+    std::sort(t, t + 3);
+    *secs = 1e-3 * t[1];
+    return PK_OK;
+}
+}  // namespace pk
+
 extern "C" {
 
 int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
@@ -78,8 +112,10 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
         return fail(PK_ERR_INVALID_ARG, "null argument or negative group count");
     if (dtype != PK_F32 && dtype != PK_BF16) return fail(PK_ERR_UNSUPPORTED_DTYPE, "grouped products: f32 or bf16");
     if (tbl->device < 0) return fail(PK_ERR_INVALID_ARG, "grouped plans need a table bound to a device");
-    if (policy != PK_POLICY_CASE && policy != PK_POLICY_LEARNED)
-        return fail(PK_ERR_INVALID_ARG, "grouped plans: policy CASE or LEARNED");
+    if (policy != PK_POLICY_CASE && policy != PK_POLICY_LEARNED && policy != PK_POLICY_EXHAUSTIVE)
+        return fail(PK_ERR_INVALID_ARG, "grouped plans: policy CASE, LEARNED or EXHAUSTIVE");
+    if (policy == PK_POLICY_EXHAUSTIVE && accumulate && !per_group_or_null)
+        return fail(PK_ERR_INVALID_ARG, "grouped plans: EXHAUSTIVE selection writes C, so not with accumulate");
     *out = nullptr;
     try {
         std::unique_ptr<pk_grouped_plan> plan(new pk_grouped_plan);
@@ -93,6 +129,7 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
         std::map<const KernelEntry *, std::vector<int>> by_entry;
         plan->chosen.assign(G, pk_params{});
         std::vector<std::vector<Candidate>> okc(G);
+        std::vector<std::vector<const KernelEntry *>> okg(G);  // the grouped instance of each
         for (int g = 0; g < G; ++g) {
             if (M[g] < 0 || N[g] < 0 || K[g] < 0 || M[g] > kMaxDim || N[g] > kMaxDim || K[g] > kMaxDim)
                 return fail(PK_ERR_INVALID_ARG, "bad size in product " + std::to_string(g));
@@ -103,8 +140,10 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
             const KernelEntry *ge = nullptr;
             for (const auto &c : feasible(tbl, (int)dtype, M[g], N[g], K[g]))
                 if (c.family == PK_FAMILY_MFMA &&
-                    grouped_instance((int)dtype, c.variant, part->fam.points[c.point], &ge))
+                    grouped_instance((int)dtype, c.variant, part->fam.points[c.point], &ge)) {
                     okc[g].push_back(c);
+                    okg[g].push_back(ge);
+                }
             if (okc[g].empty())
                 return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no grouped program fits product " + std::to_string(g));
         }
@@ -119,9 +158,10 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
             for (int g = 0; g < G; ++g) {
                 if (M[g] == 0 || N[g] == 0) continue;
                 ++live;
-                for (const auto &c : okc[g]) {
-                    auto &t = total[c.entry];
-                    t.first += tile_work_seconds(tbl->machine, *c.entry, (int)dtype, M[g], N[g], K[g]);
+                for (size_t i = 0; i < okc[g].size(); ++i) {
+                    // the cost of the grouped instance, which is what runs
+                    auto &t = total[okc[g][i].entry];
+                    t.first += tile_work_seconds(tbl->machine, *okg[g][i], (int)dtype, M[g], N[g], K[g]);
                     t.second += 1;
                 }
             }
@@ -131,6 +171,34 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
                     plan_entry = kv.first;
                     best = kv.second.first;
                 }
+            if (policy == PK_POLICY_EXHAUSTIVE && live > 0) {
+                // time a plan of each program that fits every product on the
+                // plan's own operands, keep the fastest
+                std::vector<const KernelEntry *> fits;
+                for (const auto &kv : total)
+                    if (kv.second.second == live) fits.push_back(kv.first);
+                std::vector<pk_params> ps(G);
+                double best_s = 0.0;
+                for (const KernelEntry *e : fits) {
+                    for (int g = 0; g < G; ++g) {
+                        if (M[g] == 0 || N[g] == 0) continue;
+                        for (const auto &c : okc[g])
+                            if (c.entry == e) fill_params(tbl, c, (int)dtype, &ps[g]);
+                    }
+                    pk_grouped_plan *trial = nullptr;
+                    int rc = pk_grouped_plan_create(tbl, dtype, G, M, N, K, A, lda, B, ldb, C, ldc, ps.data(),
+                                                    PK_POLICY_CASE, 0, &trial);
+                    if (rc != PK_OK) return rc;
+                    std::unique_ptr<pk_grouped_plan> owned(trial);
+                    double secs = 0.0;
+                    rc = time_plan(trial, &secs);
+                    if (rc != PK_OK) return rc;
+                    if (e == fits.front() || secs < best_s) {
+                        best_s = secs;
+                        plan_entry = e;
+                    }
+                }
+            }
         }
         for (int g = 0; g < G; ++g) {
             if (M[g] == 0 || N[g] == 0) continue;

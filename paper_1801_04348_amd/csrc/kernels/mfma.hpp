@@ -577,14 +577,36 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
-// Many independent products in one launch: workgroups stride over the global
-// tile index; tile t belongs to group tile_group[t] and is tile
-// t - tile_start of that group, numbered row-major over its tiles.
+// Many independent products in one launch; tile t belongs to group
+// tile_group[t] and is tile t - tile_start of that group, numbered row-major
+// over its tiles (a product's tiles are consecutive).  Workgroup b runs on XCD
+// b % 8, so XCD x is given the contiguous tile range [x T / 8, (x + 1) T / 8),
+// which its workgroups stride over: a product's tiles then share one XCD's L2
+// (striding over all tiles would spread them over every XCD and fetch the same
+// panels into eight caches).  Grids of fewer than 8 workgroups stride over all
+// tiles.
+struct GroupWalk {
+    int64_t t, end, stride;
+    __device__ __forceinline__ explicit GroupWalk(int64_t total) {
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        if (G < XCDS) {
+            t = b;
+            end = total;
+            stride = G;
+        } else {
+            const int64_t x = b % XCDS;
+            t = total * x / XCDS + b / XCDS;
+            end = total * (x + 1) / XCDS;
+            stride = (G - x + XCDS - 1) / XCDS;  // workgroups on XCD x
+        }
+    }
+};
+
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
-    for (int64_t t = blockIdx.x; t < g.total_tiles; t += gridDim.x) {
-        const GroupDesc &d = g.descs[g.tile_group[t]];
-        const int64_t local = t - d.tile_start;
+    for (GroupWalk w(g.total_tiles); w.t < w.end; w.t += w.stride) {
+        const GroupDesc &d = g.descs[g.tile_group[w.t]];
+        const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
@@ -594,9 +616,9 @@ __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
-    for (int64_t t = blockIdx.x; t < g.total_tiles; t += gridDim.x) {
-        const GroupDesc &d = g.descs[g.tile_group[t]];
-        const int64_t local = t - d.tile_start;
+    for (GroupWalk w(g.total_tiles); w.t < w.end; w.t += w.stride) {
+        const GroupDesc &d = g.descs[g.tile_group[w.t]];
+        const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();

@@ -128,6 +128,28 @@ def test_given_per_group_params(table):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_exhaustive_plan_picks_a_fitting_program(table, dtype):
+    dims, host, dev = make_groups(64, seed=13, dtype=dtype, aligned_every=2, hi=300)
+    As, Bs, Cs = zip(*dev)
+    plan = pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs, policy=pk.PK_POLICY_EXHAUSTIVE)
+    n_launch, tiles, chosen = plan.info()
+    assert n_launch == 1
+    names = {pk.pk_kernel_name(table, c, dtype) for c in chosen}
+    assert len(names) == 1, names
+    say("%s exhaustive grouped pick: %s" % (dtype, names.pop()))
+    for c in Cs:
+        c.fill_(float("nan"))              # the selection runs wrote C; start again
+    plan.run()
+    torch.cuda.synchronize()
+    tol = 1e-5 if dtype == "f32" else 1e-2
+    for g, ((a, b), (ad, bd, cd)) in enumerate(zip(host, dev)):
+        assert rel_fro(cd.cpu().numpy(), om.matmul(a, b, dtype)) <= tol, (g, dims[g])
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs, policy=pk.PK_POLICY_EXHAUSTIVE, accumulate=True)
+    assert e.value.code == pk.PK_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_4096_products_sampled(table, dtype):
     G = 4096
     dims = inputs.group_dims(G, seed=0)
