@@ -171,6 +171,10 @@ def main():
                     help="run a 256 MiB device copy three times first (known bytes, for counter calibration), then "
                          "once right before and once right after the timed steps (they delimit the timed "
                          "region's dispatches in a profile; see paper_1801_04348_amd/profwindow.py)")
+    ap.add_argument("--save-picks", default=None, help="write the program chosen for each sweep shape (JSON)")
+    ap.add_argument("--load-picks", default=None,
+                    help="run the programs a previous run chose (its --save-picks file) instead of selecting: "
+                         "profiling runs then time the same launches as that run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the product path has no multi-GPU part; run with --gpus 1",
@@ -204,6 +208,8 @@ def main():
         sys.exit("no usable cost model: %s" % (model_note or MODEL))
     policy_name = "learned" if have_model and args.policy != "case" else "case"
     policy = pk.PK_POLICY_LEARNED if policy_name == "learned" else pk.PK_POLICY_CASE
+    if args.load_picks:
+        policy_name = "picks of a previous run (%s)" % os.path.basename(args.load_picks)
     shapes = inputs.sweep_shapes()
     big = max(max(s) for s in shapes)
     Abuf = inputs.uniform_f32((big * big,), seed=0).cuda()
@@ -223,16 +229,23 @@ def main():
             marker()
         torch.cuda.synchronize()
     ops = []
+    picks = None
+    if args.load_picks:
+        with open(args.load_picks) as f:
+            picks = {tuple(r["shape"]): pk.params(**r["params"]) for r in json.load(f)}
     for (M, N, K) in shapes:
-        p = pk.pk_select(tbl, "f32", M, N, K, policy, allow_fallback=True)
+        p = picks[(M, N, K)] if picks else pk.pk_select(tbl, "f32", M, N, K, policy, allow_fallback=True)
         ops.append(dict(M=M, N=N, K=K, A=Abuf[:M * K].view(M, K), B=Bbuf[:K * N].view(K, N),
                         C=Cbuf[:M * N].view(M, N), p=p, name=pk.pk_kernel_name(tbl, p, "f32"),
                         flops=2.0 * M * N * K))
     flops_step = sum(o["flops"] for o in ops)
+    if args.save_picks:
+        with open(args.save_picks, "w") as f:
+            json.dump([{"shape": [o["M"], o["N"], o["K"]], "params": o["p"].as_dict()} for o in ops], f)
 
     def one_pass(events=None):
         for o in ops:
-            p = pk.pk_select(tbl, "f32", o["M"], o["N"], o["K"], policy, allow_fallback=True)
+            p = o["p"] if picks else pk.pk_select(tbl, "f32", o["M"], o["N"], o["K"], policy, allow_fallback=True)
             if events is not None and o["name"] == dominant:
                 e0, e1 = events.pop()
                 e0.record()
