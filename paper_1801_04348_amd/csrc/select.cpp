@@ -108,8 +108,9 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     // VALU K steps also pay their two barriers per resident workgroup
     const double overhead = mfma ? 0.0 : 0.4e-6 * (double)res;
     // element loads instead of 16-byte loads (rows not aligned): measured
-    // about 1.3x (f32) and 1.5x (bf16) slower per step
-    const double narrow = (mfma && !wide) ? (dtype == PK_BF16 ? 1.5 : 1.3) : 1.0;
+    // about 1.4x (f32) and 3.5x (bf16) slower per step, measured with the
+    // same programs both ways at 2048^3 and 4096^3
+    const double narrow = (mfma && !wide) ? (dtype == PK_BF16 ? 3.5 : 1.4) : 1.0;
     const double compute =
         narrow * (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
     const double es = elem_bytes(dtype);

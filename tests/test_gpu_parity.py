@@ -102,23 +102,23 @@ def test_machine_query_matches_runtime_props():
     assert m.arch.decode().startswith("gfx950")
 
 
-# ---------------------------------------------------------------- cfg1: f32 256^3
-CFG1_E = [(bx, by, s) for bx in (8, 16, 32) for by in (8, 16, 32) for s in (1, 2, 4)]
+# ---------------------------------------------------------------- f32 256^3
+F32_256_E = [(bx, by, s) for bx in (8, 16, 32) for by in (8, 16, 32) for s in (1, 2, 4)]
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def f32_256():
     A = inputs.uniform_f32((256, 256), seed=0)
     B = inputs.uniform_f32((256, 256), seed=1)
     return dev(A), dev(B), om.matmul(A, B, "f32")
 
 
-@pytest.mark.parametrize("E", CFG1_E)
-def test_cfg1_every_leaf_and_variant(table, fit, cfg1, E):
-    A, B, ref = cfg1
+@pytest.mark.parametrize("E", F32_256_E)
+def test_f32_256_every_leaf_and_variant(table, fit, f32_256, E):
+    A, B, ref = f32_256
     bx, by, s = E
     leaf, var = pk.pk_case_table_lookup(table, "f32", pk.params(bx=bx, by=by, s=s))
-    say("cfg1 E=%s leaf=%d variant=%d" % (E, leaf, var))
+    say("f32 256^3 E=%s leaf=%d variant=%d" % (E, leaf, var))
     C = run(table, pk.params(leaf=leaf, bx=bx, by=by, s=s), "f32", A, B, 256, 256)
     assert rel_fro(C.numpy(), ref) <= F32_TOL
     for v in VALU_VARIANTS:  # forced: every program where it fits
@@ -126,24 +126,24 @@ def test_cfg1_every_leaf_and_variant(table, fit, cfg1, E):
         assert C is None or rel_fro(C.numpy(), ref) <= F32_TOL, (E, v)
 
 
-# ---------------------------------------------------------------- cfg2: i32 1024^3
-CFG2_B = (4, 8, 16, 32)
+# ---------------------------------------------------------------- i32 1024^3
+I32_1024_B = (4, 8, 16, 32)
 
 
 @pytest.fixture(scope="module")
-def cfg2():
+def i32_1024():
     A = inputs.small_int_i32((1024, 1024), seed=0)
     B = inputs.small_int_i32((1024, 1024), seed=1)
     return dev(A), dev(B), om.matmul(A, B, "i32")
 
 
-@pytest.mark.parametrize("bx", CFG2_B)
-@pytest.mark.parametrize("by", CFG2_B)
-def test_cfg2_every_leaf_and_variant_bit_exact(table, fit, cfg2, bx, by):
-    A, B, ref = cfg2
+@pytest.mark.parametrize("bx", I32_1024_B)
+@pytest.mark.parametrize("by", I32_1024_B)
+def test_i32_1024_every_leaf_and_variant_bit_exact(table, fit, i32_1024, bx, by):
+    A, B, ref = i32_1024
     for s in (1, 2, 4, 8):
         leaf, var = pk.pk_case_table_lookup(table, "i32", pk.params(bx=bx, by=by, s=s))
-        say("cfg2 E=(%d,%d,%d) leaf=%d variant=%d" % (bx, by, s, leaf, var))
+        say("i32 1024^3 E=(%d,%d,%d) leaf=%d variant=%d" % (bx, by, s, leaf, var))
         C = run(table, pk.params(leaf=leaf, bx=bx, by=by, s=s), "i32", A, B, 1024, 1024, out_dtype=torch.int32)
         assert np.array_equal(C.numpy(), ref)
         for v in VALU_VARIANTS:
