@@ -353,6 +353,32 @@ def test_unaligned_rows_take_element_loads(table, fit, desc, dtype):
     assert rel_fro(C.numpy(), ref) <= tol
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (3, 9, 5), (7, 1, 33), (65, 3, 70)])
+def test_tiny_unaligned_shapes_every_twin(table, fit, desc, dtype, M, N, K):
+    # packed operands of these shapes have unaligned rows, so every MFMA
+    # program runs as its element-load twin: every step is an edge step
+    # (rows and columns clamped, k beyond K read from the zero block); a plain
+    # and an accumulating run against the oracle
+    A = inputs.uniform_f32((M, K), seed=91 + M)
+    B = inputs.uniform_f32((K, N), seed=92 + N)
+    if dtype == "bf16":
+        A, B = inputs.bf16_bits(A), inputs.bf16_bits(B)
+    C0 = inputs.uniform_f32((M, N), seed=93)
+    ref = om.matmul(A, B, dtype)
+    ref_acc = om.matmul(A, B, dtype, Cin=C0.double().numpy())
+    tol = F32_TOL if dtype == "f32" else BF16_TOL
+    for pt in mfma_points(desc, dtype):
+        for v in MFMA_VARIANTS:
+            if not fit(1, dtype, v, pt) or (dtype == "bf16" and pt[0] * pt[1] >= 256 * 256):
+                continue
+            say("mfma %s twin %s variant %d on %dx%dx%d" % (dtype, pt, v, M, N, K))
+            C = run(table, mfma_params(pt, v), dtype, dev(A), dev(B), M, N)
+            assert rel_fro(C.numpy(), ref) <= tol, (pt, v)
+            C = run(table, mfma_params(pt, v), dtype, dev(A), dev(B), M, N, accumulate=True, C0=dev(C0))
+            assert rel_fro(C.numpy(), ref_acc) <= tol, (pt, v)
+
+
 # ---------------------------------------------------------------- full sizes, CASE pick (as benchmarked)
 def sampled_check(A, B, C, dtype, nsamp=48, seed=0):
     """Sampled elements against the oracle, one by one: the relative RMS error
