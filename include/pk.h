@@ -259,8 +259,10 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
  * (one launch; the latency of a single product does not count when the
  * products run side by side).  `policy` PK_POLICY_CASE or PK_POLICY_LEARNED
  * makes that choice; PK_POLICY_EXHAUSTIVE instead builds a plan of each
- * program that fits every product, times it on the device (one untimed run,
- * median of three) and keeps the fastest -- those runs write C, so it is
+ * program that could run every product -- each point whose case-table leaf
+ * holds for all of them, with each LDS-stage variant whose resources fit, as
+ * a forced variant would run -- times it on the device (one untimed run,
+ * median of three) and keeps the fastest; those runs write C, so it is
  * refused (PK_ERR_INVALID_ARG) together with accumulate.  Rows that are not
  * aligned for the 16-byte loads are read with element loads.  The plan copies its descriptors to the device when created
  * (allocating and synchronizing then); running it allocates nothing and does

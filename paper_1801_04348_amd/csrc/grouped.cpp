@@ -172,32 +172,48 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
                     best = kv.second.first;
                 }
             if (policy == PK_POLICY_EXHAUSTIVE && live > 0) {
-                // time a plan of each program that fits every product on the
-                // plan's own operands, keep the fastest
-                std::vector<const KernelEntry *> fits;
-                for (const auto &kv : total)
-                    if (kv.second.second == live) fits.push_back(kv.first);
-                std::vector<pk_params> ps(G);
+                // the auto-tuner over the programs that could run every
+                // product: each point whose case-table leaf holds for all of
+                // them, with each LDS-stage variant whose resources fit (as a
+                // forced variant would run); a plan of each is timed on the
+                // plan's own operands and the fastest kept
+                bool have = false;
+                pk_params best_p{};
                 double best_s = 0.0;
-                for (const KernelEntry *e : fits) {
-                    for (int g = 0; g < G; ++g) {
-                        if (M[g] == 0 || N[g] == 0) continue;
-                        for (const auto &c : okc[g])
-                            if (c.entry == e) fill_params(tbl, c, (int)dtype, &ps[g]);
-                    }
-                    pk_grouped_plan *trial = nullptr;
-                    int rc = pk_grouped_plan_create(tbl, dtype, G, M, N, K, A, lda, B, ldb, C, ldc, ps.data(),
-                                                    PK_POLICY_CASE, 0, &trial);
-                    if (rc != PK_OK) return rc;
-                    std::unique_ptr<pk_grouped_plan> owned(trial);
-                    double secs = 0.0;
-                    rc = time_plan(trial, &secs);
-                    if (rc != PK_OK) return rc;
-                    if (e == fits.front() || secs < best_s) {
-                        best_s = secs;
-                        plan_entry = e;
+                for (const auto &kv : total) {
+                    if (kv.second.second != live) continue;
+                    const KernelEntry *e = kv.first;
+                    for (int v : {0, (int)PK_MFMA_SINGLE}) {
+                        pk_params proto{};
+                        proto.family = PK_FAMILY_MFMA;
+                        proto.leaf = -1;
+                        proto.variant = v;
+                        proto.bm = e->bm;
+                        proto.bn = e->bn;
+                        proto.bk = e->bk;
+                        proto.wm = e->wm;
+                        proto.wn = e->wn;
+                        const std::vector<pk_params> ps(G, proto);
+                        pk_grouped_plan *trial = nullptr;
+                        int rc = pk_grouped_plan_create(tbl, dtype, G, M, N, K, A, lda, B, ldb, C, ldc, ps.data(),
+                                                        PK_POLICY_CASE, 0, &trial);
+                        if (rc == PK_ERR_NO_FEASIBLE_BRANCH || rc == PK_ERR_NOT_INSTANTIATED) continue;
+                        if (rc != PK_OK) return rc;
+                        std::unique_ptr<pk_grouped_plan> owned(trial);
+                        double secs = 0.0;
+                        rc = time_plan(trial, &secs);
+                        if (rc != PK_OK) return rc;
+                        if (!have || secs < best_s) {
+                            have = true;
+                            best_s = secs;
+                            best_p = proto;
+                        }
                     }
                 }
+                if (!have) return fail(PK_ERR_NO_FEASIBLE_BRANCH, "no grouped program fits every product");
+                const std::vector<pk_params> ps(G, best_p);
+                return pk_grouped_plan_create(tbl, dtype, G, M, N, K, A, lda, B, ldb, C, ldc, ps.data(), PK_POLICY_CASE,
+                                              0, out);
             }
         }
         for (int g = 0; g < G; ++g) {
