@@ -376,7 +376,11 @@ int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t
 int pk_probe_valu_rate(const pk_table *tbl, pk_dtype dtype, double *ops_per_second);
 
 /* Analytic launch shape of a choice: grid and block sizes and LDS bytes the
- * kernel of *p uses for an MxN output.  Errors as pk_matmul (no launch). */
+ * kernel of *p uses for an MxN output, by the table's machine model.  A
+ * launch on a device sizes the grids of workgroup-stride programs by the HIP
+ * runtime's occupancy calculator instead, which can hold more workgroups
+ * resident than the model (some runtimes report a block register budget of
+ * half the register file).  Errors as pk_matmul (no launch). */
 int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N,
                     int64_t K, int64_t *grid, int32_t *block, int64_t *lds_bytes);
 

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <sstream>
 #include <stdexcept>
 
@@ -99,6 +101,35 @@ int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N)
     return std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)m.cu_count * blocks_per_cu(m, e)));
 }
 
+// Resident workgroups of a kernel per compute unit for a launch on the
+// current device: the HIP runtime's occupancy calculator, which reads the
+// kernel's actual register, LDS and wave needs against the hardware (some
+// runtimes report a block register budget of half the register file, which
+// the case table's model uses as reported); cached per kernel.  Falls back
+// to the model's count if the query fails.
+int64_t live_blocks_per_cu(const pk_machine &m, const KernelEntry &e) {
+    static std::mutex mu;
+    static std::map<const void *, int64_t> cache;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(e.fn);
+        if (it != cache.end()) return it->second;
+    }
+    int n = 0;
+    int64_t b = blocks_per_cu(m, e);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, e.fn, e.threads, 0) == hipSuccess && n > 0) b = n;
+    else (void)hipGetLastError();
+    std::lock_guard<std::mutex> lock(mu);
+    cache[e.fn] = b;
+    return b;
+}
+
+int64_t launch_grid(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N) {
+    const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
+    if (e.family == PK_FAMILY_MFMA) return tiles;
+    return std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)m.cu_count * live_blocks_per_cu(m, e)));
+}
+
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Rows aligned for the MFMA programs' wide loads: 16-byte loads along the
@@ -119,7 +150,7 @@ int launch(const pk_machine &m, const KernelEntry &e0, const MmArgs &args, hipSt
         if (!pe) return fail(PK_ERR_NOT_INSTANTIATED, std::string("no element-load twin of ") + e0.name);
     }
     const KernelEntry &e = *pe;
-    const int64_t grid = grid_of(m, e, args.M, args.N);
+    const int64_t grid = launch_grid(m, e, args.M, args.N);
     if (grid <= 0) return PK_OK;
     if (grid > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "grid too large");
     MmArgs a = args;

@@ -278,7 +278,7 @@ int pk_grouped_plan_create(const pk_table *tbl, pk_dtype dtype, int32_t G, const
             L.ndesc = (int64_t)descs.size() - L.first_desc;
             L.total_tiles = tiles;
             L.grid = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)tbl->machine.cu_count *
-                                                                       blocks_per_cu(tbl->machine, *e)));
+                                                                       live_blocks_per_cu(tbl->machine, *e)));
             plan->launches.push_back(L);
         }
         plan->ndesc = (int64_t)descs.size();

@@ -20,7 +20,7 @@ namespace {
 
 int run_steps(const pk_machine &m, const KernelEntry &e, void *a, int64_t N, int64_t steps, size_t elem,
               hipStream_t stream) {
-    const int64_t grid = grid_of(m, e, 1, N - 2);
+    const int64_t grid = launch_grid(m, e, 1, N - 2);
     char *lo = static_cast<char *>(a), *hi = lo + (size_t)N * elem;
     for (int64_t t = 0; t < steps; ++t) {
         // even steps write the second half from the first, odd steps the reverse
@@ -74,7 +74,7 @@ std::vector<int> fused_plan(int64_t steps) {
 
 int run_fused(const pk_machine &m, const KernelEntry &e, void *a, int64_t N, int64_t steps, size_t elem,
               hipStream_t stream) {
-    const int64_t grid = grid_of(m, e, 1, N - 2);
+    const int64_t grid = launch_grid(m, e, 1, N - 2);
     char *half[2] = {static_cast<char *>(a), static_cast<char *>(a) + (size_t)N * elem};
     int cur = 0;  // the half holding the current state: the first before step 0
     for (int k : fused_plan(steps)) {

@@ -16,7 +16,7 @@ namespace pk {
 namespace {
 
 int launch_ma(const pk_machine &m, const KernelEntry &e, const pkk::MaArgs &args, hipStream_t stream) {
-    const int64_t grid = grid_of(m, e, args.M, args.N);
+    const int64_t grid = launch_grid(m, e, args.M, args.N);
     pkk::MaArgs a = args;
     void *kargs[] = {&a};
     hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);

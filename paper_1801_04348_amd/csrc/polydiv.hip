@@ -27,7 +27,7 @@ uint64_t barrett_mu(uint32_t P) { return (uint64_t)((((unsigned __int128)1) << 6
 int run_division(const pk_machine &m, const KernelEntry &e, uint32_t *a, int64_t N, const uint32_t *b, int64_t M,
                  uint32_t P, hipStream_t stream) {
     if (N <= M) return PK_OK;
-    const int64_t grid = grid_of(m, e, 1, M);
+    const int64_t grid = launch_grid(m, e, 1, M);
     pkk::PdArgs g{a, b, (int32_t)M, 0, P, barrett_mu(P)};
     for (int64_t n = N; n - 1 >= M; --n) {
         g.n = (int32_t)n;
@@ -63,7 +63,7 @@ const KernelEntry *find_fused(const pk_machine &m, int64_t B, int64_t S, int64_t
 int run_fused(const pk_machine &m, const KernelEntry &e, uint32_t *a, int64_t N, const uint32_t *b, int64_t M,
               uint32_t P, hipStream_t stream) {
     if (N <= M) return PK_OK;
-    const int64_t grid = grid_of(m, e, 1, M);
+    const int64_t grid = launch_grid(m, e, 1, M);
     pkk::PdArgs g{a, b, (int32_t)M, (int32_t)N, P, barrett_mu(P)};
     void *kargs[] = {&g};
     hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);

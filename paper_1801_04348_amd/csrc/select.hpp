@@ -65,6 +65,9 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
 // helpers shared with capi.cpp
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);
 int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
+// the same for a launch: residency from the runtime's occupancy calculator
+int64_t live_blocks_per_cu(const pk_machine &m, const KernelEntry &e);
+int64_t launch_grid(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
 bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb);
 int launch(const pk_machine &m, const KernelEntry &e, const MmArgs &args, hipStream_t stream);
 void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *out);

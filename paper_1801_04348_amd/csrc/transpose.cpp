@@ -18,7 +18,7 @@ namespace pk {
 namespace {
 
 int launch_tr(const pk_machine &m, const KernelEntry &e, const pkk::TrArgs &args, hipStream_t stream) {
-    const int64_t grid = grid_of(m, e, args.M, args.N);
+    const int64_t grid = launch_grid(m, e, args.M, args.N);
     pkk::TrArgs a = args;
     void *kargs[] = {&a};
     hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);
