@@ -50,12 +50,18 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     // also reads 1 + s LDS words per s multiply-adds, which caps it near 24
     // multiply-adds per clock, rising slowly with s; the direct kernel is
     // bound by global/L1 reads (about one multiply-add per clock).
+    // int32 (fitted on 200 random int32 shapes): the tiled kernel's rate
+    // peaks at s = 2 and falls at s = 8, where each work-item holds eight
+    // running sums and their operands; relative rates 0.85, 1, 0.95, 0.70 for
+    // s = 1, 2, 4, 8 of the 32 multiply-adds per clock.
     const double s = std::max(1, e.s);
     double mads = dtype == PK_I32 ? 32.0 : 64.0;
-    if (!(e.variant & PK_VALU_NOLDS))
-        mads = std::min(mads, 24.0 * std::pow(s / (1.0 + s), 0.25));
-    else
+    if (e.variant & PK_VALU_NOLDS)
         mads = 1.0;
+    else if (dtype == PK_I32)
+        mads *= e.s <= 1 ? 0.85 : e.s == 2 ? 1.0 : e.s <= 4 ? 0.95 : 0.70;
+    else
+        mads = std::min(mads, 24.0 * std::pow(s / (1.0 + s), 0.25));
     return 2.0 * mads * lanes;
 }
 }  // namespace
@@ -97,8 +103,9 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double ksteps = (double)((std::max<int64_t>(K, 1) + bk - 1) / bk);
     const double flops_step = 2.0 * e.tile_m * e.tile_n * bk;
     const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
-    const double occupancy = std::min(1.0, std::pow(waves_per_simd / 3.0, 0.25));
     const bool mfma = e.family == PK_FAMILY_MFMA;
+    const bool vi32 = !mfma && dtype == PK_I32;  // int32 VALU: its own fitted knee and barrier cost
+    const double occupancy = std::min(1.0, std::pow(waves_per_simd / (vi32 ? 6.0 : 3.0), 0.25));
     // MFMA: the tile's LDS words per output; VALU: workgroups of fewer than
     // 256 work-items lose in proportion
     const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n))
@@ -106,7 +113,7 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double rate = cu_rate(m, e, dtype) * clock * eff * occupancy;
     const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.1e-6;
     // VALU K steps also pay their two barriers per resident workgroup
-    const double overhead = mfma ? 0.0 : 0.4e-6 * (double)res;
+    const double overhead = mfma ? 0.0 : (vi32 ? 0.025e-6 : 0.4e-6) * (double)res;
     // element loads instead of 16-byte loads (rows not aligned): measured
     // about 1.4x (f32) and 3.5x (bf16) slower per step, measured with the
     // same programs both ways at 2048^3 and 4096^3

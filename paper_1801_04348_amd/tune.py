@@ -8,8 +8,9 @@ choice per shape.
 Timing store (JSON lines, append-only, resumable): one record per shape
     {"machine": {...}, "dtype": "f32", "shape": [M, N, K],
      "candidates": [{"params": {...}, "name": kernel, "seconds": t}, ...]}
-Operands: the leading M*K and K*N elements of two float32 buffers filled
-i.i.d. uniform on [-1, 1) from seeds 0 and 1 (as in bench.py).
+Operands: the leading M*K and K*N elements of two buffers from seeds 0 and
+1 -- float32 uniform on [-1, 1) (as in bench.py), its bfloat16 rounding for
+bf16, full-range int32 for i32.
 Shape lists: "sweep" = the 216 shapes over {512, 1000, 2048, 3000, 4096,
 8192}^3; "random:COUNT:SEED" = COUNT shapes log-uniform on [64, 8192]^3.
 """
@@ -66,10 +67,17 @@ def main():
                 if r["dtype"] == args.dtype and r["machine"] == fp:
                     done[tuple(r["shape"])] = r
     big = max(max(max(s[0] * s[2], s[2] * s[1]), s[0] * s[1]) for s in shapes)
-    assert args.dtype == "f32", "the tuner's operand buffers are float32"
-    Abuf = inputs.uniform_f32((big,), seed=0).cuda()
-    Bbuf = inputs.uniform_f32((big,), seed=1).cuda()
-    Cbuf = torch.empty((big,), dtype=torch.float32, device="cuda")
+    if args.dtype == "i32":
+        Abuf = inputs.full_range_i32((big,), seed=0).cuda()
+        Bbuf = inputs.full_range_i32((big,), seed=1).cuda()
+        Cbuf = torch.empty((big,), dtype=torch.int32, device="cuda")
+    else:
+        Abuf = inputs.uniform_f32((big,), seed=0)
+        Bbuf = inputs.uniform_f32((big,), seed=1)
+        if args.dtype == "bf16":
+            Abuf, Bbuf = inputs.bf16_bits(Abuf), inputs.bf16_bits(Bbuf)
+        Abuf, Bbuf = Abuf.cuda(), Bbuf.cuda()
+        Cbuf = torch.empty((big,), dtype=torch.float32, device="cuda")
     t_start = time.time()
     with open(args.store, "a") as out:
         for i, (M, N, K) in enumerate(shapes):
@@ -90,7 +98,7 @@ def main():
             out.flush()
             done[(M, N, K)] = rec
             b = min(cands, key=lambda c: c["seconds"])
-            print("[%d/%d] %s: %d candidates in %.1fs, best %s %.1f GFLOP/s" % (
+            print("[%d/%d] %s: %d candidates in %.1fs, best %s %.1f GOP/s" % (
                 i + 1, len(shapes), (M, N, K), len(cands), time.time() - t0, b["name"],
                 2.0 * M * N * K / b["seconds"] / 1e9), flush=True)
     if args.best:
