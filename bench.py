@@ -204,6 +204,8 @@ def main():
             have_model = True
         except pk.PkError as e:
             model_note = str(e)
+        if have_model:
+            pk.load_shipped_models(tbl)  # the other element types' models, for the side sections
     if args.policy == "learned" and not have_model:
         sys.exit("no usable cost model: %s" % (model_note or MODEL))
     policy_name = "learned" if have_model and args.policy != "case" else "case"

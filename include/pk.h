@@ -202,8 +202,8 @@ int pk_case_table_lookup(const pk_table *tbl, pk_dtype dtype, const pk_params *p
  * system at the bound machine.  PK_POLICY_EXHAUSTIVE launches kernels on the
  * table's device on a private stream and synchronizes; its picks are cached
  * per (dtype, M, N, K) for the table's lifetime.  PK_POLICY_LEARNED needs a
- * model loaded with pk_costmodel_load (else PK_ERR_COST_MODEL and *out holds
- * the CASE pick).  Errors: PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_INVALID_ARG. */
+ * model for dtype given to the table (pk_case_table_set_costmodel; else
+ * PK_ERR_COST_MODEL and *out holds the CASE pick).  Errors: PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_INVALID_ARG. */
 int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int policy,
               pk_params *out);
 
@@ -427,9 +427,9 @@ int pk_costmodel_train(const pk_table *tbl, const float *X, const float *seconds
 int pk_costmodel_predict(const pk_costmodel *cm, int device, const float *X, int64_t n, float *log_seconds);
 
 /* The network's raw forward/backward on the device: mean squared error of
- * the network with parameters `params` (host, 4929 floats in the order W1
- * (64x10), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x 10, host) and
- * targets t (host); writes the gradient (4929 floats) and the loss.  Used to
+ * the network with parameters `params` (host, 4993 floats in the order W1
+ * (64x11), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x 11, host) and
+ * targets t (host); writes the gradient (4993 floats) and the loss.  Used to
  * check the kernels against a float64 reference. */
 int pk_costmodel_grad(int device, const float *params, const float *X, const float *t, int64_t n, float *grad,
                       float *loss);
@@ -438,21 +438,32 @@ int pk_costmodel_grad(int device, const float *params, const float *X, const flo
  * place; step >= 1 is the step number used for bias correction). */
 int pk_costmodel_adam_step(int device, float *params, const float *grad, float *m, float *v, int64_t step, float lr);
 
-/* Parameter export (*n = 4929; out may be NULL to query), text save/load
- * (the file carries the standardisation and the machine it was trained on),
- * release, and the machine fingerprint string. */
+/* Parameter export (*n = 4993; out may be NULL to query), text save/load
+ * (the file carries the standardisation, the machine and the element type
+ * it was trained on; a file without a dtype line is float32), release, and
+ * the machine fingerprint string. */
 int pk_costmodel_params(const pk_costmodel *cm, float *out, int cap, int *n);
 int pk_costmodel_save(const pk_costmodel *cm, const char *path);
 int pk_costmodel_load(const char *path, pk_costmodel **out);
 void pk_costmodel_free(pk_costmodel *cm);
 const char *pk_costmodel_machine(const pk_costmodel *cm);
 
-/* Gives the table a copy of the model for PK_POLICY_LEARNED.  A model whose
- * machine differs from the table's is refused (PK_ERR_COST_MODEL).  The
- * LEARNED policy orders the feasible candidates by predicted time; when the
- * best two differ by less than 5 %, every candidate predicted within 5 % of
- * the best is timed (as pk_measure does) and the fastest kept.  Not to be
- * called while other threads select on the same table. */
+/* The element type whose timings the model was trained on (a pk_dtype;
+ * pk_costmodel_train leaves it PK_F32, the trainer sets it from its data):
+ * LEARNED selections use a model only for that type.  Errors:
+ * PK_ERR_INVALID_ARG (null), PK_ERR_UNSUPPORTED_DTYPE. */
+int pk_costmodel_dtype(const pk_costmodel *cm);
+int pk_costmodel_set_dtype(pk_costmodel *cm, pk_dtype dtype);
+
+/* Gives the table a copy of the model for PK_POLICY_LEARNED on the model's
+ * element type, replacing the table's model for that type (NULL removes
+ * every model).  A model whose machine differs from the table's is refused
+ * (PK_ERR_COST_MODEL).  The LEARNED policy orders the feasible candidates by
+ * predicted time; when the best two differ by less than 5 %, every candidate
+ * predicted within 5 % of the best is timed (as pk_measure does) and the
+ * fastest kept; for a type with no model it returns the CASE pick with
+ * PK_ERR_COST_MODEL.  Not to be called while other threads select on the
+ * same table. */
 int pk_case_table_set_costmodel(pk_table *tbl, const pk_costmodel *cm);
 
 /* LEARNED selections made on the table and how many fell back to timing. */

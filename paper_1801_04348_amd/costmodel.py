@@ -6,8 +6,9 @@
 train: one row per (shape, candidate) of the stores (written by tune.py on
 this device): the library's features of the candidate (pk_features) and its
 measured seconds; the network is trained on the device by the library
-(pk_costmodel_train) and saved with its standardisation and the machine it
-was trained on.
+(pk_costmodel_train) and saved with its standardisation, the machine and the
+element type it was trained on (one model per type; the stores must not mix
+types).
 
 eval: for every shape of a held-out store, the LEARNED choice as pk_select
 makes it -- the candidate with the least predicted time, except that when the
@@ -93,6 +94,11 @@ def main():
     if not recs:
         sys.exit("no timing records for this machine in %s" % args.store)
 
+    dtypes = {r["dtype"] for r in recs}
+    if len(dtypes) != 1:
+        sys.exit("the stores mix element types %s: one model per type" % sorted(dtypes))
+    dtype = dtypes.pop()
+
     if args.cmd == "train":
         Xs, ts = zip(*(feature_rows(pk, tbl, r) for r in recs))
         X = np.concatenate(Xs).astype(np.float32)
@@ -101,15 +107,19 @@ def main():
         t0 = time.perf_counter()
         cm, loss = pk.pk_costmodel_train(tbl, X, t, epochs=args.epochs, lr=args.lr, seed=args.seed)
         train_s = time.perf_counter() - t0
+        cm.set_dtype(dtype)
         pred = cm.predict(X)
         rmse = float(np.sqrt(np.mean((pred - np.log(t)) ** 2)))
         cm.save(args.out)
-        print(json.dumps({"rows": int(X.shape[0]), "shapes": len(recs), "epochs": args.epochs, "lr": args.lr,
+        print(json.dumps({"dtype": dtype, "rows": int(X.shape[0]), "shapes": len(recs), "epochs": args.epochs,
+                          "lr": args.lr,
                           "loss_standardised": loss, "rmse_ln_seconds": rmse, "train_seconds": round(train_s, 3),
                           "ms_per_epoch": round(train_s / args.epochs * 1e3, 4), "model": args.out}), flush=True)
         return
 
     cm = pk.pk_costmodel_load(args.model)
+    if cm.dtype() != dtype:
+        sys.exit("the model was trained on %s timings, the store holds %s" % (cm.dtype(), dtype))
     pk.pk_case_table_set_costmodel(tbl, cm)
     import time
     learned, model_only, case, fallbacks, measured, infer = [], [], [], 0, 0, []
@@ -134,7 +144,7 @@ def main():
         wide = pk.packed_rows_wide(r["dtype"], N, K)
         est = [pk.pk_estimate(tbl, pk.params(**c["params"]), r["dtype"], M, N, K, wide) for c in r["candidates"]]
         case.append(best / t[int(np.argmin(est))])
-    out = {"learned": stats(learned), "learned_without_measurement": stats(model_only), "case": stats(case),
+    out = {"dtype": dtype, "learned": stats(learned), "learned_without_measurement": stats(model_only), "case": stats(case),
            "fallback_rate": fallbacks / len(recs), "candidates_measured_per_fallback": measured / max(fallbacks, 1),
            "margin": MARGIN, "predict_ms_per_shape": round(1e3 * sum(infer) / len(infer), 4), "model": args.model}
     out["learned_over_case_geomean"] = out["learned"]["geomean"] / out["case"]["geomean"]

@@ -236,6 +236,7 @@ struct pk_costmodel {
     float xmean[PK_NFEATURES], xstd[PK_NFEATURES];
     float ymean = 0.f, ystd = 1.f;        // of ln(seconds)
     std::string fingerprint;              // machine the timings came from
+    int dtype = PK_F32;                   // element type the timings came from
     int epochs = 0;
     float loss = 0.f;
 };
@@ -476,7 +477,8 @@ int pk_costmodel_save(const pk_costmodel *cm, const char *path) {
     std::ofstream f(path);
     if (!f) return fail(PK_ERR_INVALID_ARG, std::string("cannot write ") + path);
     f.precision(9);
-    f << "pk-costmodel 1\n" << "features " << PK_NFEATURES << "\n" << "machine " << cm->fingerprint << "\n";
+    f << "pk-costmodel 1\n" << "features " << PK_NFEATURES << "\n" << "machine " << cm->fingerprint << "\n"
+      << "dtype " << (cm->dtype == PK_I32 ? "i32" : cm->dtype == PK_BF16 ? "bf16" : "f32") << "\n";
     f << "epochs " << cm->epochs << "\nloss " << cm->loss << "\nxmean";
     for (float v : cm->xmean) f << " " << v;
     f << "\nxstd";
@@ -500,6 +502,14 @@ int pk_costmodel_load(const char *path, pk_costmodel **out) {
     while (f >> key) {
         if (key == "features") f >> nf;
         else if (key == "machine") f >> cm->fingerprint;
+        else if (key == "dtype") {  // absent: float32 (files written before the field)
+            std::string d;
+            f >> d;
+            if (d == "f32") cm->dtype = PK_F32;
+            else if (d == "i32") cm->dtype = PK_I32;
+            else if (d == "bf16") cm->dtype = PK_BF16;
+            else return fail(PK_ERR_COST_MODEL, "unknown dtype " + d);
+        }
         else if (key == "epochs") f >> cm->epochs;
         else if (key == "loss") f >> cm->loss;
         else if (key == "xmean") for (float &v : cm->xmean) f >> v;
@@ -520,19 +530,29 @@ void pk_costmodel_free(pk_costmodel *cm) { delete cm; }
 
 const char *pk_costmodel_machine(const pk_costmodel *cm) { return cm ? cm->fingerprint.c_str() : nullptr; }
 
+int pk_costmodel_dtype(const pk_costmodel *cm) { return cm ? cm->dtype : fail(PK_ERR_INVALID_ARG, "null model"); }
+
+int pk_costmodel_set_dtype(pk_costmodel *cm, pk_dtype dtype) {
+    if (!cm) return fail(PK_ERR_INVALID_ARG, "null model");
+    if (dtype != PK_F32 && dtype != PK_I32 && dtype != PK_BF16) return fail(PK_ERR_UNSUPPORTED_DTYPE, "unknown dtype");
+    cm->dtype = (int)dtype;
+    return PK_OK;
+}
+
 int pk_case_table_set_costmodel(pk_table *tbl, const pk_costmodel *cm) {
     if (!tbl) return fail(PK_ERR_INVALID_ARG, "null table");
-    if (!cm) {
-        tbl->costmodel.reset();
-        return PK_OK;
-    }
-    if (cm->fingerprint != machine_fingerprint(tbl->machine))
+    if (cm && cm->fingerprint != machine_fingerprint(tbl->machine))
         return fail(PK_ERR_COST_MODEL, "cost model trained on " + cm->fingerprint + ", table bound to " +
                                            machine_fingerprint(tbl->machine));
-    tbl->costmodel = std::shared_ptr<pk_costmodel>(new pk_costmodel(*cm));
+    if (!cm)
+        for (auto &slot : tbl->costmodel) slot.reset();
+    else
+        tbl->costmodel[cm->dtype] = std::shared_ptr<pk_costmodel>(new pk_costmodel(*cm));
     std::lock_guard<std::mutex> g(tbl->cache_mu);
     for (auto it = tbl->cache.begin(); it != tbl->cache.end();)
-        it = std::get<4>(it->first) == PK_POLICY_LEARNED ? tbl->cache.erase(it) : std::next(it);
+        it = std::get<4>(it->first) == PK_POLICY_LEARNED && (!cm || std::get<0>(it->first) == cm->dtype)
+                 ? tbl->cache.erase(it)
+                 : std::next(it);
     return PK_OK;
 }
 

@@ -280,13 +280,14 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         }
     }
     int pick = 0;
-    if (policy == PK_POLICY_LEARNED && tbl->costmodel) {
+    const pk_costmodel *model = (dtype >= 0 && dtype < 3) ? tbl->costmodel[dtype].get() : nullptr;
+    if (policy == PK_POLICY_LEARNED && model) {
         // order by predicted time; near-ties are settled by measurement
         std::vector<float> X(cands.size() * PK_NFEATURES), pred(cands.size());
         const bool wide = !A || wide_rows(dtype, A, lda, B, ldb);
         for (size_t i = 0; i < cands.size(); ++i)
             features(tbl->machine, *cands[i].entry, M, N, K, wide, &X[i * PK_NFEATURES]);
-        costmodel_predict(*tbl->costmodel, tbl->device, X.data(), (int64_t)cands.size(), pred.data());
+        costmodel_predict(*model, tbl->device, X.data(), (int64_t)cands.size(), pred.data());
         std::vector<int> order(cands.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
@@ -320,7 +321,8 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         for (size_t i = 1; i < cands.size(); ++i)
             if (cands[i].estimate < cands[pick].estimate) pick = (int)i;
         fill_params(tbl, cands[pick], dtype, out);
-        if (policy == PK_POLICY_LEARNED) return fail(PK_ERR_COST_MODEL, "no cost model loaded; CASE pick returned");
+        if (policy == PK_POLICY_LEARNED)
+            return fail(PK_ERR_COST_MODEL, "no cost model for this dtype loaded; CASE pick returned");
     } else if (policy == PK_POLICY_EXHAUSTIVE) {
         std::vector<double> secs;
         Operands ops{A, lda, B, ldb, nullptr, 0};

@@ -162,10 +162,13 @@ def lib():
         L.pk_costmodel_machine.argtypes = [vp]
         L.pk_costmodel_machine.restype = ctypes.c_char_p
         L.pk_case_table_set_costmodel.argtypes = [vp, vp]
+        L.pk_costmodel_dtype.argtypes = [vp]
+        L.pk_costmodel_set_dtype.argtypes = [vp, i32]
         L.pk_case_table_learned_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         for name in ("pk_features", "pk_costmodel_train", "pk_costmodel_predict", "pk_costmodel_grad",
                      "pk_costmodel_adam_step", "pk_costmodel_params", "pk_costmodel_save", "pk_costmodel_load",
-                     "pk_case_table_set_costmodel", "pk_case_table_learned_stats"):
+                     "pk_case_table_set_costmodel", "pk_case_table_learned_stats", "pk_costmodel_dtype",
+                     "pk_costmodel_set_dtype"):
             getattr(L, name).restype = i32
         for name in ("pk_machine_query", "pk_co_solve", "pk_case_table_build", "pk_case_table_describe",
                      "pk_case_table_lookup", "pk_select", "pk_matmul", "pk_launch_shape", "pk_measure"):
@@ -462,6 +465,15 @@ class CostModel:
     def machine(self) -> str:
         return lib().pk_costmodel_machine(self.handle).decode()
 
+    def dtype(self) -> str:
+        """The element type whose timings the model was trained on."""
+        code = lib().pk_costmodel_dtype(self.handle)
+        _check(min(code, 0))
+        return {v: k for k, v in DTYPES.items()}[code]
+
+    def set_dtype(self, dtype):
+        _check(lib().pk_costmodel_set_dtype(self.handle, _dt(dtype)))
+
     def predict(self, X, device: int = 0):
         import numpy as np
         X, px = _fbuf(X)
@@ -483,6 +495,25 @@ def pk_costmodel_train(tbl: Table, X, seconds, epochs: int = 2000, lr: float = 3
     _check(lib().pk_costmodel_train(tbl.handle, px, ps, X.shape[0], epochs, lr, seed, ctypes.byref(h),
                                     ctypes.byref(loss)))
     return CostModel(h), loss.value
+
+
+def load_shipped_models(tbl: Table):
+    """Gives the table every cost model shipped in data/ for its machine
+    (costmodel_<dtype>_<arch>.txt); returns the element types loaded.  A
+    model for another machine is skipped."""
+    arch = pk_case_table_describe(tbl)["machine"]["arch"].split(":")[0]
+    loaded = []
+    for dt in DTYPES:
+        path = os.path.join(_HERE, "data", "costmodel_%s_%s.txt" % (dt, arch))
+        if not os.path.exists(path):
+            continue
+        try:
+            cm = pk_costmodel_load(path)
+            pk_case_table_set_costmodel(tbl, cm)
+        except PkError:
+            continue
+        loaded.append(cm.dtype())
+    return loaded
 
 
 def pk_costmodel_load(path: str) -> CostModel:

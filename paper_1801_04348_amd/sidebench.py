@@ -138,8 +138,9 @@ def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
 def valu_section(tbl, pk, torch, inputs, reps=20):
     """The VALU matmul programs against their measured ceiling
     (pk_probe_valu_rate): int32 1024^3 with small-integer entries and float32
-    256^3, CASE pick and exhaustively-best leaf, in operations per second
-    (2 M N K per product)."""
+    256^3, CASE pick, LEARNED pick (where the table has a model for the
+    type) and exhaustively-best leaf, in operations per second (2 M N K per
+    product)."""
     out = {"ceiling_f32_tflops": round(pk.pk_probe_valu_rate(tbl, "f32") / 1e12, 2),
            "ceiling_i32_tops": round(pk.pk_probe_valu_rate(tbl, "i32") / 1e12, 2)}
     for dtype, n, gen in (("i32", 1024, inputs.small_int_i32), ("f32", 256, inputs.uniform_f32)):
@@ -148,8 +149,14 @@ def valu_section(tbl, pk, torch, inputs, reps=20):
         C = torch.empty((n, n), dtype=A.dtype, device="cuda")
         ceiling = out["ceiling_%s_%s" % (dtype, "tops" if dtype == "i32" else "tflops")] * 1e12
         row = {}
-        for name, pol in (("case", pk.PK_POLICY_CASE), ("best", pk.PK_POLICY_EXHAUSTIVE)):
-            p = pk.pk_select(tbl, dtype, n, n, n, pol)
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("learned", pk.PK_POLICY_LEARNED),
+                          ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            try:
+                p = pk.pk_select(tbl, dtype, n, n, n, pol)
+            except pk.PkError as e:
+                if e.code == pk.PK_ERR_COST_MODEL:  # no model for this type on the table
+                    continue
+                raise
             pk.pk_matmul(tbl, p, dtype, A, B, C)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -179,7 +186,9 @@ def main():
     from tests import inputs
 
     torch.cuda.init()
-    print(json.dumps(run_all(pk.pk_case_table_build(0), pk, torch, inputs)), flush=True)
+    tbl = pk.pk_case_table_build(0)
+    pk.load_shipped_models(tbl)
+    print(json.dumps(run_all(tbl, pk, torch, inputs)), flush=True)
 
 
 if __name__ == "__main__":

@@ -32,6 +32,40 @@ def test_model_file_roundtrip(tmp_path):
     assert np.array_equal(pk.pk_costmodel_load(path2).params(), p)
 
 
+def test_model_dtype_roundtrip_and_per_type_selection(tmp_path):
+    # a file without a dtype line is float32; set_dtype survives save/load
+    path = str(tmp_path / "m.txt")
+    m = machines.gfx950()
+    t = pk.pk_case_table_build(0, m)
+    desc_machine = pk.pk_case_table_describe(t)["machine"]
+    finger = "%s/cu%d/lds%d/regs%d/thr%d/clk%d" % (desc_machine["arch"], desc_machine["cu_count"],
+                                                  desc_machine["lds_block"], desc_machine["regs_block"],
+                                                  desc_machine["max_threads_block"], desc_machine["clock_khz"])
+    _write_model(path, mlp.init_params(3).astype(np.float32), np.zeros(mlp.IN), np.ones(mlp.IN), 0.0, 1.0,
+                 machine=finger)
+    cm = pk.pk_costmodel_load(path)
+    assert cm.dtype() == "f32"
+    cm.set_dtype("i32")
+    path2 = str(tmp_path / "m2.txt")
+    cm.save(path2)
+    assert "dtype i32" in open(path2).read()
+    cm2 = pk.pk_costmodel_load(path2)
+    assert cm2.dtype() == "i32"
+    # the table holds a model per element type: with only an int32 model, a
+    # float32 LEARNED selection is the CASE pick with PK_ERR_COST_MODEL
+    pk.pk_case_table_set_costmodel(t, cm2)
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_select(t, "f32", 1000, 1000, 1000, pk.PK_POLICY_LEARNED)
+    assert e.value.code == pk.PK_ERR_COST_MODEL
+    p = pk.pk_select(t, "f32", 1000, 1000, 1000, pk.PK_POLICY_LEARNED, allow_fallback=True)
+    assert pk.pk_kernel_name(t, p, "f32") == pk.pk_kernel_name(t, pk.pk_select(t, "f32", 1000, 1000, 1000), "f32")
+    with open(path2.replace("m2", "bad"), "w") as f:
+        f.write(open(path2).read().replace("dtype i32", "dtype f64"))
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_costmodel_load(path2.replace("m2", "bad"))
+    assert e.value.code == pk.PK_ERR_COST_MODEL
+
+
 def test_model_file_rejects_wrong_sizes(tmp_path):
     path = str(tmp_path / "bad.txt")
     _write_model(path, np.zeros(10, np.float32), np.zeros(mlp.IN), np.ones(mlp.IN), 0, 1)
