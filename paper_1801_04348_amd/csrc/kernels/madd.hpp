@@ -60,6 +60,25 @@ __device__ __forceinline__ void madd_body(const MaArgs &a) {
         const E *br = B + (int64_t)row * a.ldb;
         E *cr = C + (int64_t)row * a.ldc;
         V va[G], vb[G];
+        // the whole row segment in range: no guards, so a work-item's G loads
+        // are in flight together (one group needs no such path)
+        if (G > 1 && col0 + TN <= N) {
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                const int col = col0 + (tx + w * BX) * VW;
+                va[w] = *reinterpret_cast<const V *>(ar + col);
+                vb[w] = *reinterpret_cast<const V *>(br + col);
+            }
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                const int col = col0 + (tx + w * BX) * VW;
+                V vc;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) vc[e] = (E)AddOp<T>::add((T)va[w][e], (T)vb[w][e]);
+                *reinterpret_cast<V *>(cr + col) = vc;
+            }
+            continue;
+        }
 #pragma unroll
         for (int w = 0; w < G; ++w) {
             const int col = col0 + (tx + w * BX) * VW;

@@ -49,12 +49,30 @@ __device__ __forceinline__ void transpose_tiled(const TrArgs &a) {
     const int64_t tiles = (int64_t)((M + TR - 1) / TR) * tiles_c;
     for (int64_t b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int row0 = (int)(b / tiles_c) * TR, col0 = (int)(b % tiles_c) * TC;
+        // interior tiles: no guards, so a work-item's S loads are all in
+        // flight before the first LDS store waits for its data (a guard per
+        // load makes each load wait for the previous one)
+        const bool interior = row0 + TR <= M && col0 + TC <= N;
+        if (interior) {
+            uint32_t v[S];
 #pragma unroll
-        for (int k = 0; k < S; ++k) {  // read: lanes along a row of A
-            const int e = t + k * NT;
-            const int r = e / TC, c = e % TC;
-            const int gr = row0 + r, gc = col0 + c;
-            if (gr < M && gc < N) tile[r][c] = A[(int64_t)gr * a.lda + gc];
+            for (int k = 0; k < S; ++k) {  // read: lanes along a row of A
+                const int e = t + k * NT;
+                v[k] = A[(int64_t)(row0 + e / TC) * a.lda + col0 + e % TC];
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const int e = t + k * NT;
+                tile[e / TC][e % TC] = v[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const int e = t + k * NT;
+                const int r = e / TC, c = e % TC;
+                const int gr = row0 + r, gc = col0 + c;
+                if (gr < M && gc < N) tile[r][c] = A[(int64_t)gr * a.lda + gc];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -62,7 +80,7 @@ __device__ __forceinline__ void transpose_tiled(const TrArgs &a) {
             const int e = t + k * NT;
             const int cr = e / TR, cc = e % TR;  // C row = A column, C column = A row
             const int gr = col0 + cr, gc = row0 + cc;
-            if (gr < N && gc < M) C[(int64_t)gr * a.ldc + gc] = tile[cc][cr];
+            if (interior || (gr < N && gc < M)) C[(int64_t)gr * a.ldc + gc] = tile[cc][cr];
         }
         __syncthreads();
     }
@@ -81,6 +99,20 @@ __device__ __forceinline__ void transpose_direct(const TrArgs &a) {
     const int64_t tiles = (int64_t)((M + TR - 1) / TR) * tiles_c;
     for (int64_t b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int row0 = (int)(b / tiles_c) * TR, col0 = (int)(b % tiles_c) * TC;
+        if (row0 + TR <= M && col0 + TC <= N) {  // interior: loads in flight together
+            uint32_t v[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const int e = t + k * NT;
+                v[k] = A[(int64_t)(row0 + e / TC) * a.lda + col0 + e % TC];
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const int e = t + k * NT;
+                C[(int64_t)(col0 + e % TC) * a.ldc + row0 + e / TC] = v[k];
+            }
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int e = t + k * NT;

@@ -16,7 +16,9 @@ namespace pk {
 namespace {
 
 int launch_ma(const pk_machine &m, const KernelEntry &e, const pkk::MaArgs &args, hipStream_t stream) {
-    const int64_t grid = launch_grid(m, e, args.M, args.N);
+    // one workgroup per tile, at most 2^31 - 1 of them (the kernel strides
+    // over any tiles beyond)
+    const int64_t grid = std::min<int64_t>(launch_grid(m, e, args.M, args.N), 0x7fffffff);
     pkk::MaArgs a = args;
     void *kargs[] = {&a};
     hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);
