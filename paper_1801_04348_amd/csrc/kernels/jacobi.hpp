@@ -53,10 +53,21 @@ __device__ __forceinline__ void jacobi_tiled(const JaArgs &a) {
     for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int p0 = b * TW;
         const int have = min(TW, n - p0) + 2;  // inputs this tile reads
+        if (have == TW + 2) {
+            // a full tile: the S loads of a work-item go out together (a
+            // guard per load makes each wait for the one before)
+            T v[S];
 #pragma unroll
-        for (int k = 0; k <= S; ++k) {
-            const int e = t + k * B;
-            if (e < have) buf[e] = in[p0 + e];
+            for (int k = 0; k < S; ++k) v[k] = in[p0 + t + k * B];
+            if (t < 2) buf[TW + t] = in[p0 + TW + t];
+#pragma unroll
+            for (int k = 0; k < S; ++k) buf[t + k * B] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k <= S; ++k) {
+                const int e = t + k * B;
+                if (e < have) buf[e] = in[p0 + e];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -77,6 +88,19 @@ __device__ __forceinline__ void jacobi_direct(const JaArgs &a) {
     const int tiles = (n + TW - 1) / TW;
     for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int p0 = b * TW;
+        if (p0 + TW <= n) {  // a full tile: loads out together
+            T x[S], y[S], z[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                const int p = p0 + t + k * B;
+                x[k] = in[p];
+                y[k] = in[p + 1];
+                z[k] = in[p + 2];
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) out[p0 + t + k * B + 1] = Avg3<T>::f(x[k], y[k], z[k]);
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int p = p0 + t + k * B;
@@ -123,9 +147,20 @@ __device__ __forceinline__ void jacobi_fused(const JfArgs &a) {
     for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
         const int g0 = 1 + b * TW;  // first interior point of the tile
         const int w0 = g0 - k;      // window start (may lie before the vector)
-        for (int i = t; i < L; i += B) {
-            const int g = w0 + i;
-            buf[0][i] = (g >= 0 && g < N) ? in[g] : T(0);
+        if (w0 >= 0 && w0 + L <= N) {
+            // the window lies inside the vector: the first S chunks (i < TW <=
+            // L) load together, then the 2k points left
+            T v[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) v[c] = in[w0 + t + c * B];
+#pragma unroll
+            for (int c = 0; c < S; ++c) buf[0][t + c * B] = v[c];
+            for (int i = TW + t; i < L; i += B) buf[0][i] = in[w0 + i];
+        } else {
+            for (int i = t; i < L; i += B) {
+                const int g = w0 + i;
+                buf[0][i] = (g >= 0 && g < N) ? in[g] : T(0);
+            }
         }
         __syncthreads();
         for (int j = 1; j <= k; ++j) {
