@@ -73,7 +73,46 @@ __device__ __forceinline__ void valu_tiled(const MmArgs &a) {
             const int col = col0 + tx + w * BX;
             acc[w] = (a.accumulate && row < M && col < N) ? Acc<T>::from(C[(int64_t)row * a.ldc + col]) : U(0);
         }
+        constexpr int UA = (TM * BK + NT - 1) / NT, UB = (BK * TN + NT - 1) / NT;
+        const bool inside = row0 + TM <= M && col0 + TN <= N;
         for (int k0 = 0; k0 < K; k0 += BK) {
+            if (inside && k0 + BK <= K) {
+                // the whole K tile in range: no guards, so a work-item's loads
+                // are all in flight before the first LDS store waits (a guard
+                // per load makes each wait for the one before)
+                T va[UA], vb[UB];
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const int e = tid + u * NT;
+                    if ((TM * BK) % NT == 0 || e < TM * BK)
+                        va[u] = A[(int64_t)(row0 + e / BK) * a.lda + k0 + e % BK];
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = tid + u * NT;
+                    if ((BK * TN) % NT == 0 || e < BK * TN)
+                        vb[u] = B[(int64_t)(k0 + e / TN) * a.ldb + col0 + e % TN];
+                }
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const int e = tid + u * NT;
+                    if ((TM * BK) % NT == 0 || e < TM * BK) As[e / BK][e % BK] = va[u];
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = tid + u * NT;
+                    if ((BK * TN) % NT == 0 || e < BK * TN) Bs[e / TN][e % TN] = vb[u];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < BK; ++kk) {
+                    const U av = (U)As[ty][kk];
+#pragma unroll
+                    for (int w = 0; w < S; ++w) acc[w] = Acc<T>::mad(acc[w], av, (U)Bs[kk][tx + w * BX]);
+                }
+                __syncthreads();
+                continue;
+            }
 #pragma unroll
             for (int u = 0; u < (TM * BK + NT - 1) / NT; ++u) {
                 const int e = tid + u * NT;
