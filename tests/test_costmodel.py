@@ -6,9 +6,10 @@ import os
 import numpy as np
 import pytest
 
+import oracle.matmul as om
 import oracle.mlp as mlp
 from paper_1801_04348_amd import pk
-from tests import machines
+from tests import inputs, machines
 
 
 def _write_model(path, params, xmean, xstd, ymean, ystd, machine="m"):
@@ -164,3 +165,33 @@ def test_training_fits_a_known_law():
     y = np.log(secs[2500:])
     r2 = 1.0 - np.mean((pred - y) ** 2) / np.var(y)
     assert r2 >= 0.99, r2
+
+
+@pytest.mark.gpu
+def test_shipped_models_pick_programs_that_match_the_oracle():
+    # the shipped models (one per element type) attach to a table bound to
+    # this device; each LEARNED pick runs and agrees with the oracle
+    import torch
+    t = pk.pk_case_table_build(0)
+    loaded = pk.load_shipped_models(t)
+    assert set(loaded) == {"f32", "i32", "bf16"}, loaded
+    for dtype, (M, N, K) in (("f32", (1000, 3000, 512)), ("i32", (300, 260, 200)), ("bf16", (512, 384, 264))):
+        if dtype == "i32":
+            A = inputs.small_int_i32((M, K), seed=5)
+            B = inputs.small_int_i32((K, N), seed=6)
+        else:
+            A = inputs.uniform_f32((M, K), seed=5)
+            B = inputs.uniform_f32((K, N), seed=6)
+            if dtype == "bf16":
+                A, B = inputs.bf16_bits(A), inputs.bf16_bits(B)
+        p = pk.pk_select(t, dtype, M, N, K, pk.PK_POLICY_LEARNED)
+        C = torch.empty((M, N), dtype=torch.int32 if dtype == "i32" else torch.float32, device="cuda")
+        pk.pk_matmul(t, p, dtype, A.cuda(), B.cuda(), C)
+        torch.cuda.synchronize()
+        ref = om.matmul(A, B, dtype)
+        got = C.cpu().numpy()
+        if dtype == "i32":
+            assert np.array_equal(got, ref), pk.pk_kernel_name(t, p, dtype)
+        else:
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert err <= (1e-5 if dtype == "f32" else 1e-2), (pk.pk_kernel_name(t, p, dtype), err)
