@@ -64,21 +64,24 @@ TR_S = (1, 2, 4, 8)
 MFMA_F32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (128, 128, 32, 2, 2),
             (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4)]
 MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128, 128, 64, 2, 2),
-             (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4)]
+             (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4),
+             (256, 128, 32, 2, 2), (128, 256, 32, 2, 2)]
 
 
 def valu_lds(bx, by, s, nolds):
     return 0 if nolds else 4 * (by * (by + 1) + by * bx * s)
 
 
-def mfma_reg_cap(dt, threads, stages, kind):
+def mfma_reg_cap(dt, threads, stages, kind, bm=0, bn=0):
     """At most 65536 / threads registers a lane, so that the workgroup fits a
     block register budget of 65536 (the smaller figure HIP runtimes report for
     gfx950), where the compiler's own choice would exceed it and the capped
     program compiles without spilling: element-load twins and grouped programs
     of 256 work-items (256 registers; their loads at chosen addresses hold
-    more), and single-stage float32 programs of 512 (128)."""
-    if (dt == F32 and threads == 512 and stages == 1) or (kind != "wide" and threads == 256):
+    more), programs of 256 work-items with tiles larger than 128 x 128 (256),
+    and single-stage float32 programs of 512 (128)."""
+    if (dt == F32 and threads == 512 and stages == 1) or (kind != "wide" and threads == 256) or \
+            (threads == 256 and bm * bn > 128 * 128):
         return "__attribute__((amdgpu_waves_per_eu(%d)))" % (threads // 128)
     return ""
 
@@ -115,7 +118,7 @@ def instances():
                 entry = dict(family=FAM_MFMA, variant=0 if stages == 2 else MFMA_SINGLE, dtype=dt,
                              bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
-                entry["attrs"] = mfma_reg_cap(dt, 64 * wm * wn, stages, "wide")
+                entry["attrs"] = mfma_reg_cap(dt, 64 * wm * wn, stages, "wide", bm, bn)
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
                 # the element-load twin, launched for rows not aligned for 16-byte
                 # loads (none for the largest bf16 tile, whose twin would spill)
@@ -123,7 +126,7 @@ def instances():
                     continue
                 body_el = "pkk::%s<%d, %d, %d, %d, %d, %d, false>(a);" % (fn, bm, bn, bk, wm, wn, stages)
                 entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT,
-                                attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "twin"))
+                                attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "twin", bm, bn))
                 # (a translation unit of its own: compiled beside the wide kernel
                 # it changes the wide kernel's instruction schedule, measurably)
                 out.append(("mfma_%s_%d_el" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
