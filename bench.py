@@ -20,6 +20,8 @@ Prints one JSON line (rank 0, the only rank):
              branch timed in the same run (untimed for `value`)
   grouped    4096 uneven products in one persistent launch per configuration
              (graph replay) against a loop of single launches
+  bf16_dense bfloat16 products at 4096^3 and 8192^3 (CASE, LEARNED and best
+             program) against the 2.5 PFLOP/s bf16 matrix peak
   side       the paper's other examples (paper_1801_04348_amd/sidebench.py):
              transposition, matrix addition, 1D Jacobi, polynomial division
 """
@@ -68,6 +70,42 @@ def cpu_baseline(budget_s: float = 20.0):
     return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": om.threads(), "kind": "oracle",
             "sample": "%d of the sweep's shapes with M,N,K <= 3000, in sweep order (%.1f GFLOP in %.1f s)"
                       % (len(done), flops / 1e9, secs)}
+
+
+def bf16_section(tbl, pk, torch, inputs):
+    """Dense bfloat16 products (float32 accumulate) at 4096^3 and 8192^3,
+    uniform[-1,1) operands rounded to bfloat16: the CASE pick, the LEARNED
+    pick (where the table has a bfloat16 model) and the exhaustively-best
+    program, against the 2.5 PFLOP/s dense bf16 matrix peak."""
+    out = {}
+    for n in (4096, 8192):
+        A = inputs.bf16_bits(inputs.uniform_f32((n, n), seed=21)).cuda()
+        B = inputs.bf16_bits(inputs.uniform_f32((n, n), seed=22)).cuda()
+        C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        row = {}
+        for name, pol in (("case", pk.PK_POLICY_CASE), ("learned", pk.PK_POLICY_LEARNED),
+                          ("best", pk.PK_POLICY_EXHAUSTIVE)):
+            try:
+                p = pk.pk_select(tbl, "bf16", n, n, n, pol)
+            except pk.PkError as e:
+                if e.code == pk.PK_ERR_COST_MODEL:
+                    continue
+                raise
+            reps = 100 if n <= 4096 else 20  # tens of milliseconds per measurement
+            for _ in range(reps // 4):          # warm-up
+                pk.pk_matmul(tbl, p, "bf16", A, B, C)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                pk.pk_matmul(tbl, p, "bf16", A, B, C)
+            e1.record()
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) / reps * 1e-3
+            row[name] = {"kernel": pk.pk_kernel_name(tbl, p, "bf16"), "tflops": round(2.0 * n ** 3 / s / 1e12, 1),
+                         "pct_bf16_peak": round(2.0 * n ** 3 / s / 2.5e15, 4)}
+        out["%dx%dx%d" % (n, n, n)] = row
+    return out
 
 
 def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
@@ -376,8 +414,10 @@ def main():
         from paper_1801_04348_amd import sidebench
         side = sidebench.run_all(tbl, pk, torch, inputs)
     grouped = None
+    bf16 = None
     if not args.sweep_only:
         grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
+        bf16 = bf16_section(tbl, pk, torch, inputs)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
@@ -387,7 +427,7 @@ def main():
                       "shapes": len(shapes), "gflop_per_step": round(flops_step / 1e9, 1), "policy": policy_name,
                       "parallelism": "none (1 GPU)"},
            "pct_fp32_peak": round(value / 1e3 / FP32_PEAK_TFLOPS, 4),
-           "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "side": side,
+           "large_shapes": large, "exhaustive": exhaustive, "grouped": grouped, "bf16_dense": bf16, "side": side,
            "roofline": roofline,
            "machine": {k: machine[k] for k in ("arch", "cu_count", "lds_block", "regs_block", "max_blocks_cu")}}
     if not args.no_cpu_baseline:
