@@ -212,10 +212,10 @@ int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t
  * cost model's training data.  A, B, C (device pointers, row-major, as in
  * pk_matmul; C is overwritten) are the operands to time on; with A == NULL
  * the call allocates scratch operands filled with a non-zero byte pattern and
- * frees them.  Each candidate is launched once untimed, once timed, and,
- * unless that launch is already 1.5x slower than the best so far, again until
- * about 20 ms (at least 3 launches); seconds_out[i] is its mean time per
- * launch.  Runs on a private stream and synchronizes.  *n receives the number
+ * frees them.  Each candidate is launched once untimed, then back to back
+ * between two events: 3 launches, and, unless their mean is already 1.5x the
+ * best so far, more until about 20 ms of work; seconds_out[i] is its mean
+ * time per launch.  Runs on a private stream and synchronizes.  *n receives the number
  * of candidates; arrays must hold cap >= *n entries (else
  * PK_ERR_BUFFER_TOO_SMALL).  MFMA candidates are timed on the given
  * operands as they are: rows not aligned for 16-byte loads are read element

@@ -22,8 +22,8 @@
 // The constants (eff's shape, step latencies) were set from event timings of
 // these kernels on gfx950; the estimate only has to rank candidates.
 // EXHAUSTIVE: every candidate is launched and timed with HIP events on the
-// device; a candidate whose first launch is already 1.5x slower than the best
-// median so far is not timed further.  The fastest is kept (cached per shape).
+// device (back-to-back launches, mean); a candidate whose first three
+// launches are already 1.5x slower than the best so far is not timed further.  The fastest is kept (cached per shape).
 #include "select.hpp"
 
 #include <algorithm>
@@ -224,21 +224,15 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
     for (size_t i = 0; i < cands.size(); ++i) {
         const KernelEntry &e = *cands[i].entry;
         if (launch(tbl->machine, e, args, s) != PK_OK) continue;  // warm-up
-        // one timed launch first: a candidate already 1.5x slower than the
-        // best so far cannot win and is not timed further
+        // back-to-back launches between two events, at least 3, up to about
+        // 20 ms of work; after the first 3 a candidate already 1.5x slower
+        // than the best so far cannot win and is not timed further (its mean
+        // over those 3 is kept: a single launch between events would also
+        // count the launch latency, which for small kernels exceeds the
+        // kernel, and would cut off candidates that could win)
         float ms = 0.f;
         hipEventRecord(e0, s);
-        launch(tbl->machine, e, args, s);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms * 1e-3 > 1.5 * best_t) {
-            (*secs)[i] = ms * 1e-3;
-            continue;
-        }
-        hipEventRecord(e0, s);
         int reps = 0;
-        // at least 3 launches, up to about 20 ms of work
         do {
             launch(tbl->machine, e, args, s);
             ++reps;
@@ -246,6 +240,7 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
                 hipEventRecord(e1, s);
                 hipEventSynchronize(e1);
                 hipEventElapsedTime(&ms, e0, e1);
+                if (reps == 3 && ms * 1e-3 / 3 > 1.5 * best_t) break;
             }
         } while (reps < 3 || (ms < 20.f && reps < 200));
         const double t = ms * 1e-3 / reps;
