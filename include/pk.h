@@ -459,8 +459,8 @@ int pk_costmodel_set_dtype(pk_costmodel *cm, pk_dtype dtype);
  * element type, replacing the table's model for that type (NULL removes
  * every model).  A model whose machine differs from the table's is refused
  * (PK_ERR_COST_MODEL).  The LEARNED policy orders the feasible candidates by
- * predicted time; when the best two differ by less than 5 %, every candidate
- * predicted within 5 % of the best is timed (as pk_measure does) and the
+ * predicted time; when the best two differ by less than 10 %, every candidate
+ * predicted within 10 % of the best is timed (as pk_measure does) and the
  * fastest kept; for a type with no model it returns the CASE pick with
  * PK_ERR_COST_MODEL.  Not to be called while other threads select on the
  * same table. */

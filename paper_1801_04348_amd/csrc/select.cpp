@@ -288,7 +288,9 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
         pick = order[0];
         tbl->learned_selections++;
-        const double margin = 0.05;
+        // about the model's error (RMSE near 0.08 in ln seconds): closer
+        // predictions than this do not order the candidates reliably
+        const double margin = 0.10;
         if (order.size() > 1 && std::exp((double)pred[order[1]] - pred[order[0]]) < 1.0 + margin) {
             std::vector<Candidate> close;
             std::vector<int> idx;
