@@ -64,3 +64,37 @@ def test_fits_log_volume():
         _, g = mlp.loss_and_grad(p, X, t)
         p = opt.step(p, g)
     assert mlp.loss_and_grad(p, X, t)[0] < 1e-3
+
+
+def test_adam_bias_correction_constant_gradient_every_step():
+    # under a constant gradient g the moments are m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2, so bias correction restores mhat = g and
+    # vhat = g^2 at every step t and each step moves lr * g / (|g| + eps);
+    # dividing by 1 - b1 (or 1 - b2) instead of 1 - b1^t moves the parameters
+    # by a different amount from t = 2 on
+    opt = mlp.Adam(3, lr=0.01)
+    p0 = np.array([0.5, -1.0, 2.0])
+    g = np.array([0.3, -4.0, 1e-2])
+    p = p0.copy()
+    for t in range(1, 7):
+        p = opt.step(p, g)
+        assert np.allclose(p, p0 - t * 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13), t
+
+
+def test_adam_two_different_gradients_by_hand():
+    # g1 = 1, g2 = -2, b1 = 0.9, b2 = 0.999, lr = 0.1, worked by hand:
+    #   m1 = 0.1, v1 = 0.001 (step 1 moves by lr: mhat = 1, vhat = 1)
+    #   m2 = 0.9 * 0.1 + 0.1 * (-2) = -0.11
+    #   v2 = 0.999 * 0.001 + 0.001 * 4 = 0.004999
+    #   mhat = -0.11 / (1 - 0.81) = -11/19
+    #   vhat = 0.004999 / (1 - 0.998001) = 4999/1999
+    opt = mlp.Adam(1, lr=0.1)
+    p = np.array([0.25])
+    p = opt.step(p, np.array([1.0]))
+    assert np.isclose(p[0], 0.25 - 0.1 / (1.0 + 1e-8), rtol=0, atol=1e-15)
+    p = opt.step(p, np.array([-2.0]))
+    assert np.isclose(opt.m[0], -0.11, rtol=0, atol=1e-15)
+    assert np.isclose(opt.v[0], 0.004999, rtol=0, atol=1e-15)
+    want = 0.25 - 0.1 / (1.0 + 1e-8) + 0.1 * (11.0 / 19.0) / (np.sqrt(4999.0 / 1999.0) + 1e-8)
+    assert np.isclose(p[0], want, rtol=0, atol=1e-14)
+    assert np.isclose(p[0], 0.1866103534720751, rtol=0, atol=1e-13)
