@@ -198,7 +198,11 @@ int pk_case_table_lookup(const pk_table *tbl, pk_dtype dtype, const pk_params *p
 
 /* ------------------------------------------------------------------ selection */
 /* Chooses a leaf and program parameters for C(MxN) = A(MxK) B(KxN) under a
- * policy and writes them to *out.  Every candidate satisfies its leaf's
+ * policy and writes them to *out: the load-time step of Section 1, where the
+ * case discussion, evaluated at the machine's parameters, fixes which
+ * programs may run, and the program parameters the paper leaves to
+ * auto-tuning are chosen by an analytic estimate (CASE), a learned cost
+ * model (LEARNED) or measurement (EXHAUSTIVE).  Every candidate satisfies its leaf's
  * system at the bound machine.  PK_POLICY_EXHAUSTIVE launches kernels on the
  * table's device on a private stream and synchronizes; its picks are cached
  * per (dtype, M, N, K) for the table's lifetime.  PK_POLICY_LEARNED needs a
@@ -207,15 +211,31 @@ int pk_case_table_lookup(const pk_table *tbl, pk_dtype dtype, const pk_params *p
 int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int policy,
               pk_params *out);
 
+/* As pk_select, for given operands (device pointers, row-major, as in
+ * pk_matmul): MFMA candidates are costed and, under EXHAUSTIVE or the LEARNED
+ * fallback, timed as the kernels pk_matmul would run on these operands -- the
+ * element-load form where rows are not aligned for 16-byte loads, and a
+ * program without one left out.  EXHAUSTIVE and the LEARNED fallback time
+ * on A and B with a scratch C they allocate; picks are not cached.  M, N > 0.
+ * Errors as pk_select, and PK_ERR_HIP. */
+int pk_select_operands(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb,
+                       int64_t M, int64_t N, int64_t K, int policy, pk_params *out);
+
 /* Times every feasible (leaf, E) for C(MxN) = A(MxK) B(KxN) on the table's
- * device -- the measurement behind PK_POLICY_EXHAUSTIVE, the tuner and the
+ * device -- the auto-tuning by which Section 1 fixes program parameters, and
+ * the measurement behind PK_POLICY_EXHAUSTIVE, the tuner and the
  * cost model's training data.  A, B, C (device pointers, row-major, as in
  * pk_matmul; C is overwritten) are the operands to time on; with A == NULL
  * the call allocates scratch operands filled with a non-zero byte pattern and
- * frees them.  Each candidate is launched once untimed, then back to back
- * between two events: 3 launches, and, unless their mean is already 1.5x the
- * best so far, more until about 20 ms of work; seconds_out[i] is its mean
- * time per launch.  Runs on a private stream and synchronizes.  *n receives the number
+ * frees them.  Candidates are timed in order of their CASE estimate, least
+ * first.  Each is launched once between two events (warm-up); if that launch
+ * took over 1 ms and twice the best mean so far, its time is that launch's;
+ * otherwise it is launched back to back between two events: 3 launches, and,
+ * unless their mean is already 1.5x the best so far, more until about 20 ms
+ * of work; seconds_out[i] (in the order of params_out) is its mean
+ * time per launch (+inf for a candidate whose launches or events failed;
+ * PK_ERR_HIP when no candidate could be timed or the timing set-up failed).
+ * Runs on a private stream and synchronizes.  *n receives the number
  * of candidates; arrays must hold cap >= *n entries (else
  * PK_ERR_BUFFER_TOO_SMALL).  MFMA candidates are timed on the given
  * operands as they are: rows not aligned for 16-byte loads are read element
@@ -240,7 +260,11 @@ int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, 
  * are aligned for it (f32: A and B 16-byte aligned, lda and ldb multiples of
  * 4; bf16: A 16-byte aligned with lda a multiple of 8, B 4-byte aligned with
  * ldb even) and element by element otherwise -- the same arithmetic in the
- * same order, so the result does not depend on the alignment.  Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
+ * same order, so the result does not depend on the alignment.  One program
+ * has no element-load form (the bfloat16 256 x 256 x 64 tile, whose
+ * element-load kernel would spill); given it with operands whose rows are not
+ * aligned, the call runs the CASE choice for those operands instead.
+ * Errors: PK_ERR_INVALID_ARG, PK_ERR_NO_FEASIBLE_BRANCH,
  * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NOT_INSTANTIATED, PK_ERR_HIP. */
 int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dtype,
               const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
@@ -459,15 +483,24 @@ int pk_costmodel_set_dtype(pk_costmodel *cm, pk_dtype dtype);
  * element type, replacing the table's model for that type (NULL removes
  * every model).  A model whose machine differs from the table's is refused
  * (PK_ERR_COST_MODEL).  The LEARNED policy orders the feasible candidates by
- * predicted time; when the best two differ by less than 10 %, every candidate
- * predicted within 10 % of the best is timed (as pk_measure does) and the
- * fastest kept; for a type with no model it returns the CASE pick with
+ * predicted time; when the best two differ by less than the table's margin
+ * (5 % unless set with pk_case_table_set_learned_margin), every candidate
+ * predicted within that margin of the best is timed (as pk_measure does) and
+ * the fastest kept; for a type with no model it returns the CASE pick with
  * PK_ERR_COST_MODEL.  Not to be called while other threads select on the
  * same table. */
 int pk_case_table_set_costmodel(pk_table *tbl, const pk_costmodel *cm);
 
+/* The LEARNED policy's measurement margin, a fraction in [0, 1] (default
+ * 0.05; 0 never measures: the model's own pick).  Forgets the table's cached
+ * LEARNED picks.  Errors: PK_ERR_INVALID_ARG.  Not to be called while other
+ * threads select on the same table. */
+int pk_case_table_set_learned_margin(pk_table *tbl, double margin);
+
 /* LEARNED selections made on the table and how many fell back to timing. */
 int pk_case_table_learned_stats(const pk_table *tbl, int64_t *selections, int64_t *fallbacks);
+/* Candidates timed by those fallbacks, in total. */
+int pk_case_table_learned_measured(const pk_table *tbl, int64_t *candidates);
 
 /* Library version string. */
 const char *pk_version(void);

@@ -362,6 +362,18 @@ int pk_select(const pk_table *tbl, pk_dtype dtype, int64_t M, int64_t N, int64_t
     }
 }
 
+int pk_select_operands(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb,
+                       int64_t M, int64_t N, int64_t K, int policy, pk_params *out) {
+    if (!tbl || !out) return fail(PK_ERR_INVALID_ARG, "null argument");
+    if (M <= 0 || N <= 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "M and N must be positive, K non-negative");
+    if (K > 0 && (!A || !B || lda < K || ldb < N)) return fail(PK_ERR_INVALID_ARG, "null A/B or lda < K or ldb < N");
+    try {
+        return select_params(tbl, (int)dtype, M, N, K, policy, false, out, K > 0 ? A : nullptr, lda, B, ldb);
+    } catch (const std::exception &ex) {
+        return fail(PK_ERR_INVALID_ARG, ex.what());
+    }
+}
+
 int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                int64_t ldc, int64_t M, int64_t N, int64_t K, pk_params *params_out, double *seconds_out, int cap,
                int *n) {
@@ -375,8 +387,9 @@ int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, 
         if (cap < (int)cands.size()) return fail(PK_ERR_BUFFER_TOO_SMALL, "cap below the number of candidates");
         std::vector<double> secs;
         Operands ops{A, lda, B, ldb, C, ldc};
-        if (time_candidates(tbl, (int)dtype, M, N, K, cands, &secs, A ? &ops : nullptr) < 0)
-            return fail(PK_ERR_HIP, "no candidate could be launched");
+        int best = -1;
+        const int rc = time_candidates(tbl, (int)dtype, M, N, K, cands, &secs, A ? &ops : nullptr, &best);
+        if (rc != PK_OK) return rc;
         for (size_t i = 0; i < cands.size(); ++i) {
             if (params_out) fill_params(tbl, cands[i], (int)dtype, &params_out[i]);
             if (seconds_out) seconds_out[i] = secs[i];
@@ -464,8 +477,18 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
         const KernelEntry *e = nullptr;
         int rc = resolve(tbl, params_or_null, (int)dtype, &q, &e);
         if (rc != PK_OK) return rc;
-        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0,
-                    wide_rows((int)dtype, A, lda, B, ldb) ? 1 : 0};
+        const bool wide = wide_rows((int)dtype, A, lda, B, ldb);
+        if (e->family == PK_FAMILY_MFMA && !wide && !element_twin(*e)) {
+            // a program with no element-load form (it would spill) on rows
+            // not aligned for its wide loads: the CASE choice for these
+            // operands runs instead (pk_select, which sees no operands, may
+            // return such a program)
+            rc = select_params(tbl, (int)dtype, M, N, K, PK_POLICY_CASE, false, &sel, A, lda, B, ldb);
+            if (rc != PK_OK) return rc;
+            rc = resolve(tbl, &sel, (int)dtype, &q, &e);
+            if (rc != PK_OK) return rc;
+        }
+        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0, wide ? 1 : 0};
         return launch(tbl->machine, *e, args, (hipStream_t)hip_stream);
     } catch (const std::exception &ex) {
         return fail(PK_ERR_INVALID_ARG, ex.what());

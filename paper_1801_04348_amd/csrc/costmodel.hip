@@ -23,9 +23,11 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 #include <random>
 #include <sstream>
 #include <stdexcept>
+#include <tuple>
 
 #include "pk_internal.hpp"
 #include "select.hpp"
@@ -560,6 +562,22 @@ int pk_case_table_learned_stats(const pk_table *tbl, int64_t *selections, int64_
     if (!tbl) return fail(PK_ERR_INVALID_ARG, "null table");
     if (selections) *selections = tbl->learned_selections.load();
     if (fallbacks) *fallbacks = tbl->learned_fallbacks.load();
+    return PK_OK;
+}
+
+int pk_case_table_learned_measured(const pk_table *tbl, int64_t *candidates) {
+    if (!tbl || !candidates) return fail(PK_ERR_INVALID_ARG, "null argument");
+    *candidates = tbl->learned_measured.load();
+    return PK_OK;
+}
+
+int pk_case_table_set_learned_margin(pk_table *tbl, double margin) {
+    if (!tbl) return fail(PK_ERR_INVALID_ARG, "null table");
+    if (!(margin >= 0.0 && margin <= 1.0)) return fail(PK_ERR_INVALID_ARG, "margin outside [0, 1]");
+    tbl->learned_margin = margin;
+    std::lock_guard<std::mutex> g(tbl->cache_mu);
+    for (auto it = tbl->cache.begin(); it != tbl->cache.end();)
+        it = std::get<4>(it->first) == PK_POLICY_LEARNED ? tbl->cache.erase(it) : std::next(it);
     return PK_OK;
 }
 

@@ -174,7 +174,10 @@ const KernelEntry *find_polydiv_fused(int variant, int64_t bx, int64_t s);
 // The bound case table (opaque in the C ABI).
 struct pk_table {
     std::shared_ptr<pk_costmodel> costmodel[3];  // for PK_POLICY_LEARNED, per pk_dtype, or null
-    mutable std::atomic<int64_t> learned_selections{0}, learned_fallbacks{0};
+    mutable std::atomic<int64_t> learned_selections{0}, learned_fallbacks{0}, learned_measured{0};
+    // LEARNED: candidates predicted within this fraction of the best are
+    // measured when the best two are that close (0 never measures)
+    double learned_margin = 0.05;
     pk_machine machine;
     int device = -1;
     struct Part {

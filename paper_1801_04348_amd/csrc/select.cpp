@@ -22,8 +22,10 @@
 // The constants (eff's shape, step latencies) were set from event timings of
 // these kernels on gfx950; the estimate only has to rank candidates.
 // EXHAUSTIVE: every candidate is launched and timed with HIP events on the
-// device (back-to-back launches, mean); a candidate whose first three
-// launches are already 1.5x slower than the best so far is not timed further.  The fastest is kept (cached per shape).
+// device (back-to-back launches, mean), the least CASE estimate first; a
+// candidate whose first three launches are already 1.5x slower than the best
+// so far is not timed further, nor one whose single warm-up launch takes over
+// a millisecond and twice the best.  The fastest is kept (cached per shape).
 #include "select.hpp"
 
 #include <algorithm>
@@ -180,14 +182,33 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
     return out;
 }
 
-// Times every candidate on the table's device; returns the index of the fastest.
+// Times every candidate on the table's device.  Every HIP call is checked: a
+// candidate whose launches or events fail is recorded as +inf (it can never
+// be the pick), and a failure of the timing set-up itself is returned.
 int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
-                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops) {
-    if (tbl->device < 0) throw std::runtime_error("timing needs a table bound to a device");
+                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops, int *best_out) {
+    *best_out = -1;
+    secs->assign(cands.size(), std::numeric_limits<double>::infinity());
+    if (tbl->device < 0) return fail(PK_ERR_INVALID_ARG, "timing needs a table bound to a device");
     hipError_t err = hipSetDevice(tbl->device);
-    if (err != hipSuccess) throw std::runtime_error(std::string("hipSetDevice: ") + hipGetErrorString(err));
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(err));
     const size_t es = dtype == PK_BF16 ? 2 : 4;
     void *sA = nullptr, *sB = nullptr, *sC = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        if (sA) (void)hipFree(sA);
+        if (sB) (void)hipFree(sB);
+        if (sC) (void)hipFree(sC);
+    };
+    auto setup_failed = [&](const char *what, hipError_t e) {
+        release();
+        return fail(PK_ERR_HIP, std::string("timing set-up, ") + what + ": " + hipGetErrorString(e));
+    };
     MmArgs args{nullptr, nullptr, nullptr, K, N, N, (int32_t)M, (int32_t)N, (int32_t)K, 0, 0};
     if (ops && ops->A) {
         args.A = ops->A;
@@ -201,29 +222,44 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
         // float32 and bfloat16), so the timed kernels do real arithmetic
         const size_t bA = std::max<size_t>(es * M * K, 16), bB = std::max<size_t>(es * K * N, 16),
                      bC = std::max<size_t>(4 * M * N, 16);
-        if (hipMalloc(&sA, bA) != hipSuccess || hipMalloc(&sB, bB) != hipSuccess || hipMalloc(&sC, bC) != hipSuccess) {
-            hipFree(sA);
-            hipFree(sB);
-            throw std::runtime_error("timing: device allocation failed");
-        }
-        hipMemset(sA, 0x3c, bA);
-        hipMemset(sB, 0x3c, bB);
+        if ((err = hipMalloc(&sA, bA)) != hipSuccess) return setup_failed("hipMalloc", err);
+        if ((err = hipMalloc(&sB, bB)) != hipSuccess) return setup_failed("hipMalloc", err);
+        if ((err = hipMalloc(&sC, bC)) != hipSuccess) return setup_failed("hipMalloc", err);
+        if ((err = hipMemset(sA, 0x3c, bA)) != hipSuccess) return setup_failed("hipMemset", err);
+        if ((err = hipMemset(sB, 0x3c, bB)) != hipSuccess) return setup_failed("hipMemset", err);
         args.A = sA;
         args.B = sB;
         args.C = sC;
     }
     args.vec = wide_rows(dtype, args.A, args.lda, args.B, args.ldb) ? 1 : 0;
-    hipStream_t s;
-    hipEvent_t e0, e1;
-    hipStreamCreate(&s);
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    if ((err = hipStreamCreate(&s)) != hipSuccess) return setup_failed("hipStreamCreate", err);
+    if ((err = hipEventCreate(&e0)) != hipSuccess) return setup_failed("hipEventCreate", err);
+    if ((err = hipEventCreate(&e1)) != hipSuccess) return setup_failed("hipEventCreate", err);
     int best = -1;
     double best_t = std::numeric_limits<double>::infinity();
-    secs->assign(cands.size(), std::numeric_limits<double>::infinity());
-    for (size_t i = 0; i < cands.size(); ++i) {
+    // the most promising candidates first (least CASE estimate), so that the
+    // best time so far is known early and slow candidates are cut short
+    std::vector<size_t> order(cands.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return cands[x].estimate < cands[y].estimate; });
+    for (size_t i : order) {
         const KernelEntry &e = *cands[i].entry;
-        if (launch(tbl->machine, e, args, s) != PK_OK) continue;  // warm-up
+        // warm-up launch, itself timed: a candidate whose one launch already
+        // takes over a millisecond (launch latency is then negligible) and
+        // twice the best mean so far cannot win; its one-launch time is kept
+        float wms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess || launch(tbl->machine, e, args, s) != PK_OK ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&wms, e0, e1) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s);
+            continue;
+        }
+        if (wms > 1.f && wms * 1e-3 > 2.0 * best_t) {
+            (*secs)[i] = wms * 1e-3;
+            continue;
+        }
         // back-to-back launches between two events, at least 3, up to about
         // 20 ms of work; after the first 3 a candidate already 1.5x slower
         // than the best so far cannot win and is not timed further (its mean
@@ -231,18 +267,23 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
         // count the launch latency, which for small kernels exceeds the
         // kernel, and would cut off candidates that could win)
         float ms = 0.f;
-        hipEventRecord(e0, s);
+        bool ok = hipEventRecord(e0, s) == hipSuccess;
         int reps = 0;
-        do {
-            launch(tbl->machine, e, args, s);
+        while (ok) {
+            ok = launch(tbl->machine, e, args, s) == PK_OK;
             ++reps;
-            if (reps == 3 || reps % 8 == 0) {
-                hipEventRecord(e1, s);
-                hipEventSynchronize(e1);
-                hipEventElapsedTime(&ms, e0, e1);
-                if (reps == 3 && ms * 1e-3 / 3 > 1.5 * best_t) break;
+            if (ok && (reps == 3 || reps % 8 == 0)) {
+                ok = hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                if (ok && reps == 3 && ms * 1e-3 / 3 > 1.5 * best_t) break;
             }
-        } while (reps < 3 || (ms < 20.f && reps < 200));
+            if (reps >= 3 && (ms >= 20.f || reps >= 200)) break;
+        }
+        if (!ok || !(ms > 0.f)) {
+            (void)hipGetLastError();  // this candidate only: leave it at +inf
+            (void)hipStreamSynchronize(s);
+            continue;
+        }
         const double t = ms * 1e-3 / reps;
         (*secs)[i] = t;
         if (t < best_t) {
@@ -250,14 +291,12 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
             best = (int)i;
         }
     }
-    hipStreamSynchronize(s);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(s);
-    hipFree(sA);
-    hipFree(sB);
-    hipFree(sC);
-    return best;
+    err = hipStreamSynchronize(s);
+    release();
+    if (err != hipSuccess) return fail(PK_ERR_HIP, std::string("timing: ") + hipGetErrorString(err));
+    if (best < 0) return fail(PK_ERR_HIP, "no candidate could be launched and timed");
+    *best_out = best;
+    return PK_OK;
 }
 
 int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, int policy, bool cache,
@@ -288,10 +327,10 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
         pick = order[0];
         tbl->learned_selections++;
-        // about the model's error (RMSE near 0.08 in ln seconds): closer
-        // predictions than this do not order the candidates reliably
-        const double margin = 0.10;
-        if (order.size() > 1 && std::exp((double)pred[order[1]] - pred[order[0]]) < 1.0 + margin) {
+        // candidates predicted within the table's margin of the best (5 % by
+        // default) are too close for the model to order: they are measured
+        const double margin = tbl->learned_margin;
+        if (margin > 0.0 && order.size() > 1 && std::exp((double)pred[order[1]] - pred[order[0]]) < 1.0 + margin) {
             std::vector<Candidate> close;
             std::vector<int> idx;
             for (int i : order)
@@ -308,10 +347,13 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
                 ops.C = C;
                 ops.ldc = N;
             }
-            const int f = time_candidates(tbl, dtype, M, N, K, close, &secs, A ? &ops : nullptr);
-            if (C) hipFree(C);
-            if (f >= 0) pick = idx[f];
+            int f = -1;
+            const int rc = time_candidates(tbl, dtype, M, N, K, close, &secs, A ? &ops : nullptr, &f);
+            if (C) (void)hipFree(C);
+            if (rc != PK_OK) return rc;
+            pick = idx[f];
             tbl->learned_fallbacks++;
+            tbl->learned_measured += (int64_t)close.size();
         }
         fill_params(tbl, cands[pick], dtype, out);
     } else if (policy == PK_POLICY_CASE || policy == PK_POLICY_LEARNED) {
@@ -330,9 +372,9 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
             ops.C = C;
             ops.ldc = N;
         }
-        pick = time_candidates(tbl, dtype, M, N, K, cands, &secs, A ? &ops : nullptr);
-        if (C) hipFree(C);
-        if (pick < 0) return fail(PK_ERR_HIP, "no candidate could be launched");
+        const int rc = time_candidates(tbl, dtype, M, N, K, cands, &secs, A ? &ops : nullptr, &pick);
+        if (C) (void)hipFree(C);
+        if (rc != PK_OK) return rc;
         fill_params(tbl, cands[pick], dtype, out);
     } else {
         return fail(PK_ERR_INVALID_ARG, "unknown policy");

@@ -58,9 +58,11 @@ struct Operands {
 };
 
 // Times every candidate (HIP events on a private stream); secs[i] is the
-// mean time per launch of candidate i.  Returns the fastest.
+// mean time per launch of candidate i (+inf where its launches or events
+// failed).  Returns PK_OK with *best the index of the fastest, or an error
+// (PK_ERR_HIP when the timing set-up fails or no candidate could be timed).
 int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
-                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops);
+                    const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops, int *best);
 
 // helpers shared with capi.cpp
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);

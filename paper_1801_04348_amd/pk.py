@@ -122,6 +122,8 @@ def lib():
                                 i32, vp]
         L.pk_launch_shape.argtypes = [vp, ctypes.POINTER(pk_params), i32, i64, i64, i64,
                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
+        L.pk_select_operands.argtypes = [vp, i32, vp, i64, vp, i64, i64, i64, i64, i32, ctypes.POINTER(pk_params)]
+        L.pk_select_operands.restype = i32
         L.pk_measure.argtypes = [vp, i32, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.POINTER(pk_params),
                                  ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(ctypes.c_int)]
         L.pk_transpose.argtypes = [vp, ctypes.POINTER(pk_params), i32, vp, i64, vp, i64, i64, i64, vp]
@@ -165,9 +167,12 @@ def lib():
         L.pk_costmodel_dtype.argtypes = [vp]
         L.pk_costmodel_set_dtype.argtypes = [vp, i32]
         L.pk_case_table_learned_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.pk_case_table_learned_measured.argtypes = [vp, ctypes.POINTER(i64)]
+        L.pk_case_table_set_learned_margin.argtypes = [vp, ctypes.c_double]
         for name in ("pk_features", "pk_costmodel_train", "pk_costmodel_predict", "pk_costmodel_grad",
                      "pk_costmodel_adam_step", "pk_costmodel_params", "pk_costmodel_save", "pk_costmodel_load",
                      "pk_case_table_set_costmodel", "pk_case_table_learned_stats", "pk_costmodel_dtype",
+                     "pk_case_table_learned_measured", "pk_case_table_set_learned_margin",
                      "pk_costmodel_set_dtype"):
             getattr(L, name).restype = i32
         for name in ("pk_machine_query", "pk_co_solve", "pk_case_table_build", "pk_case_table_describe",
@@ -266,14 +271,30 @@ def pk_select(tbl: Table, dtype, M: int, N: int, K: int, policy: int = PK_POLICY
     return out
 
 
+def pk_select_operands(tbl: Table, dtype, A, B, policy: int = PK_POLICY_CASE, allow_fallback: bool = False):
+    """pk_select for these device operands (A: (M, K), B: (K, N)): MFMA
+    candidates as they would run on them (element loads on unaligned rows)."""
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError("shape mismatch: A %s, B %s" % (tuple(A.shape), tuple(B.shape)))
+    (a, lda), (b, ldb) = _operands((A, _in_bytes(dtype), "A"), (B, _in_bytes(dtype), "B"))
+    out = pk_params()
+    rc = lib().pk_select_operands(tbl.handle, _dt(dtype), a, lda, b, ldb, M, N, K, policy, ctypes.byref(out))
+    if rc == PK_ERR_COST_MODEL and allow_fallback:
+        return out
+    _check(rc)
+    return out
+
+
 def pk_measure(tbl: Table, dtype, M: int, N: int, K: int, A=None, B=None, C=None):
     """[(pk_params, seconds per launch)] for every feasible candidate, timed on
     the given device tensors (or on scratch operands when A is None)."""
     if A is not None:
-        a, lda = _ptr_ld(A)
-        b, ldb = _ptr_ld(B)
-        c, ldc = _ptr_ld(C)
-        lda, ldb, ldc = max(lda, K), max(ldb, N), max(ldc, N)
+        if tuple(A.shape) != (M, K) or tuple(B.shape) != (K, N) or tuple(C.shape) != (M, N):
+            raise ValueError("operand shapes do not match M, N, K")
+        (a, lda), (b, ldb), (c, ldc) = _operands((A, _in_bytes(dtype), "A"), (B, _in_bytes(dtype), "B"),
+                                                 (C, 4, "C"))
     else:
         a = b = c = None
         lda = ldb = ldc = 0
@@ -300,10 +321,9 @@ def pk_transpose(tbl: Table, p, dtype, A, C, stream=None):
     M, N = A.shape
     if tuple(C.shape) != (N, M):
         raise ValueError("C must be (N, M)")
-    a, lda = _ptr_ld(A)
-    c, ldc = _ptr_ld(C)
-    _check(lib().pk_transpose(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
-                              c, max(ldc, M), M, N, _stream(stream)))
+    (a, lda), (c, ldc) = _operands((A, 4, "A"), (C, 4, "C"))
+    _check(lib().pk_transpose(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, lda,
+                              c, ldc, M, N, _stream(stream)))
 
 
 def pk_select_madd(tbl: Table, dtype, M: int, N: int, policy: int = PK_POLICY_CASE) -> pk_params:
@@ -317,11 +337,9 @@ def pk_madd(tbl: Table, p, dtype, A, B, C, stream=None):
     M, N = A.shape
     if tuple(B.shape) != (M, N) or tuple(C.shape) != (M, N):
         raise ValueError("A, B and C must have the same shape")
-    a, lda = _ptr_ld(A)
-    b, ldb = _ptr_ld(B)
-    c, ldc = _ptr_ld(C)
-    _check(lib().pk_madd(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, max(lda, N),
-                         b, max(ldb, N), c, max(ldc, N), M, N, _stream(stream)))
+    (a, lda), (b, ldb), (c, ldc) = _operands((A, 4, "A"), (B, 4, "B"), (C, 4, "C"))
+    _check(lib().pk_madd(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype), a, lda,
+                         b, ldb, c, ldc, M, N, _stream(stream)))
 
 
 def pk_select_jacobi1d(tbl: Table, dtype, N: int, policy: int = PK_POLICY_CASE, steps: int = 1) -> pk_params:
@@ -384,11 +402,42 @@ def pk_launch_shape(tbl: Table, p: pk_params, dtype, M: int, N: int, K: int):
     return g.value, b.value, l.value
 
 
-def _ptr_ld(t):
-    """Device pointer and leading dimension of a row-major 2-D tensor."""
-    if t.dim() != 2 or t.stride(1) != 1:
-        raise ValueError("matrices must be 2-D with unit column stride")
-    return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+def _ptr_ld(t, esize=None, what="matrix", device=True):
+    """Device pointer and leading dimension of a row-major 2-D device tensor.
+
+    Raises ValueError unless the tensor is 2-D with unit column stride, its
+    rows do not overlap (stride(0) >= columns when it has several rows, so an
+    expand()ed operand or an aliased output is refused), its elements have
+    `esize` bytes (when given) and it lives on the GPU.  The leading dimension
+    passed on is the tensor's own row stride (for a single row, which is the
+    only row read, at least its column count)."""
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D, got %d dimensions" % (what, t.dim()))
+    rows, cols = int(t.shape[0]), int(t.shape[1])
+    if cols > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have unit column stride (stride %s)" % (what, tuple(t.stride())))
+    if rows > 1 and t.stride(0) < cols:
+        raise ValueError("%s rows overlap: row stride %d < %d columns" % (what, t.stride(0), cols))
+    if esize is not None and t.element_size() != esize:
+        raise ValueError("%s has %d-byte elements, the dtype needs %d" % (what, t.element_size(), esize))
+    if device and not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (got device %s)" % (what, t.device))
+    ld = t.stride(0) if rows > 1 else max(t.stride(0), cols)
+    return ctypes.c_void_p(t.data_ptr()), ld
+
+
+def _operands(*specs):
+    """[(pointer, ld)] for (tensor, element bytes, name) triples: every
+    layout is checked before any device, so a malformed operand is reported
+    as such whatever the others are."""
+    for t, es, what in specs:
+        _ptr_ld(t, es, what, device=False)
+    return [_ptr_ld(t, es, what) for t, es, what in specs]
+
+
+def _in_bytes(dtype) -> int:
+    """Bytes per element of the operands A and B of a product of this dtype."""
+    return 2 if _dt(dtype) == PK_BF16 else 4
 
 
 def _stream(stream):
@@ -406,12 +455,9 @@ def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=No
     K2, N = B.shape
     if K2 != K or tuple(C.shape) != (M, N):
         raise ValueError("shape mismatch: A %s, B %s, C %s" % (tuple(A.shape), tuple(B.shape), tuple(C.shape)))
-    a, lda = _ptr_ld(A)
-    b, ldb = _ptr_ld(B)
-    c, ldc = _ptr_ld(C)
+    (a, lda), (b, ldb), (c, ldc) = _operands((A, _in_bytes(dtype), "A"), (B, _in_bytes(dtype), "B"), (C, 4, "C"))
     _check(lib().pk_matmul(tbl.handle, ctypes.byref(p) if p is not None else None, _dt(dtype),
-                           a, max(lda, K), b, max(ldb, N), c, max(ldc, N), M, N, K,
-                           1 if accumulate else 0, _stream(stream)))
+                           a, lda, b, ldb, c, ldc, M, N, K, 1 if accumulate else 0, _stream(stream)))
 
 
 # ---------------------------------------------------------------------- cost model
@@ -561,8 +607,20 @@ def pk_case_table_learned_stats(tbl: Table):
     return a.value, b.value
 
 
+def pk_case_table_learned_measured(tbl: Table) -> int:
+    """Candidates timed by the LEARNED policy's fallbacks, in total."""
+    n = ctypes.c_int64(0)
+    _check(lib().pk_case_table_learned_measured(tbl.handle, ctypes.byref(n)))
+    return n.value
+
+
+def pk_case_table_set_learned_margin(tbl: Table, margin: float):
+    """The LEARNED policy's measurement margin (default 0.05; 0: never measure)."""
+    _check(lib().pk_case_table_set_learned_margin(tbl.handle, float(margin)))
+
+
 # ---------------------------------------------------------------------- many products
-def _grouped_arrays(As, Bs, Cs):
+def _grouped_arrays(As, Bs, Cs, dtype):
     G = len(As)
     if not (len(Bs) == len(Cs) == G):
         raise ValueError("As, Bs, Cs must have the same length")
@@ -576,11 +634,10 @@ def _grouped_arrays(As, Bs, Cs):
         if k2 != k or tuple(C.shape) != (m, n):
             raise ValueError("shape mismatch in product %d" % g)
         M[g], N[g], K[g] = m, n, k
-        pa, la = _ptr_ld(A)
-        pb, lb = _ptr_ld(B)
-        pc, lc = _ptr_ld(C)
+        (pa, la), (pb, lb), (pc, lc) = _operands((A, _in_bytes(dtype), "A[%d]" % g),
+                                                 (B, _in_bytes(dtype), "B[%d]" % g), (C, 4, "C[%d]" % g))
         a[g], b[g], c[g] = pa.value, pb.value, pc.value
-        lda[g], ldb[g], ldc[g] = max(la, k), max(lb, n), max(lc, n)
+        lda[g], ldb[g], ldc[g] = la, lb, lc
     return G, (M, N, K, a, lda, b, ldb, c, ldc)
 
 
@@ -636,7 +693,7 @@ def pk_grouped_plan_create(tbl: Table, dtype, As, Bs, Cs, params=None, policy: i
                            accumulate: bool = False) -> GroupedPlan:
     L = lib()
     _grouped_sigs(L)
-    G, arrs = _grouped_arrays(As, Bs, Cs)
+    G, arrs = _grouped_arrays(As, Bs, Cs, dtype)
     ps = None
     if params is not None:
         ps = (pk_params * G)(*params)
@@ -649,6 +706,6 @@ def pk_grouped_plan_create(tbl: Table, dtype, As, Bs, Cs, params=None, policy: i
 def pk_matmul_batched(tbl: Table, dtype, As, Bs, Cs, params=None, stream=None):
     L = lib()
     _grouped_sigs(L)
-    G, arrs = _grouped_arrays(As, Bs, Cs)
+    G, arrs = _grouped_arrays(As, Bs, Cs, dtype)
     ps = (pk_params * G)(*params) if params is not None else None
     _check(L.pk_matmul_batched(tbl.handle, _dt(dtype), G, *arrs, ps, _stream(stream)))

@@ -339,9 +339,9 @@ def test_unaligned_rows_take_element_loads(table, fit, desc, dtype):
         for v in MFMA_VARIANTS:
             say("mfma %s unaligned %s variant %d" % (dtype, pt, v))
             if dtype == "bf16" and pt[0] * pt[1] >= 256 * 256 and fit(1, dtype, v, pt):
-                with pytest.raises(pk.PkError) as e:     # no element-load twin for this tile
-                    run(table, mfma_params(pt, v), dtype, Au, Bu, M, N)
-                assert e.value.code == pk.PK_ERR_NOT_INSTANTIATED
+                # no element-load form of this tile: the CASE choice for these operands runs
+                C = run(table, mfma_params(pt, v), dtype, Au, Bu, M, N)
+                assert rel_fro(C.numpy(), ref) <= tol, (pt, v)
                 continue
             Cu = forced(table, fit, 1, dtype, v, pt, mfma_params(pt, v), Au, Bu, M, N)
             if Cu is None:
