@@ -107,8 +107,11 @@ def test_measure_and_exhaustive_pick(table, dtype, shape):
     assert len(res) == feasible_count(table, dtype), (len(res), feasible_count(table, dtype))
     secs = np.array([s for _, s in res])
     assert np.all(np.isfinite(secs)) and np.all(secs > 0), secs
+    # distinct (leaf, E) pairs; two of them may run one compiled program (a
+    # point whose leaf reduces the granularity runs the s = 1 instance)
+    keys = [tuple(sorted(p.as_dict().items())) for p, _ in res]
+    assert len(set(keys)) == len(keys)
     names = [pk.pk_kernel_name(table, p, dtype) for p, _ in res]
-    assert len(set(names)) == len(names)
     # the fastest measured candidate and the EXHAUSTIVE pick both compute the product
     fastest = res[int(np.argmin(secs))][0]
     check(table, fastest, dtype, A, B, ref, Ad, Bd)
