@@ -11,6 +11,11 @@ enumeration over a grid of machines and the whole program-parameter domain:
   thread), {gran, nolds} and {nolds} (no LDS).  LDS bytes of a tiled program:
   4 * (by * (bk + 1) + bk * bx * s') with s' its outputs per thread; threads:
   bx * by.
+* 2-D VALU family (Fig. 4's kernel with outputs per work-item along M too):
+  program parameters bx, by, s (outputs per work-item along N), sy (along
+  M), bk (the LDS tiles' K extent, free of by); programs {} and {gran} (one
+  output per work-item, s = sy = 1).  LDS bytes: 4 * (by * sy' * (bk + 1) +
+  bk * bx * s'); threads: bx * by.
 * MFMA family: program parameters bm, bn, bk, wm, wn; programs {} (two LDS
   stages) and {single} (one).  One stage holds, in float32, an A tile bm x
   (bk + 4) and a B tile bk x (bn + 4); in bfloat16 an A tile bm x (bk + 8) and
@@ -55,7 +60,7 @@ import numpy as np
 from . import comprehensive as co
 
 F32, I32, BF16 = 0, 1, 2
-VALU, MFMA, TRANSPOSE, MADD, JACOBI, POLYDIV = 0, 1, 2, 3, 4, 5
+VALU, MFMA, TRANSPOSE, MADD, JACOBI, POLYDIV, VALU2 = 0, 1, 2, 3, 4, 5, 6
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 ELEMENT = 4                 # MFMA: the twin instance reading rows element by element
@@ -63,6 +68,7 @@ ELEMENT = 4                 # MFMA: the twin instance reading rows element by el
 VALU_VARIANTS = (0, GRAN, GRAN | NOLDS, NOLDS)
 MFMA_VARIANTS = (0, SINGLE)
 MADD_VARIANTS = (0, GRAN)
+VALU2_VARIANTS = (0, GRAN)
 
 # machine grid: LDS bytes per workgroup, registers per workgroup, threads per workgroup
 LDS_GRID = (4 * 1024, 16 * 1024, 48 * 1024, 64 * 1024, 160 * 1024)
@@ -82,6 +88,11 @@ def valu_lds(variant: int, bx: int, by: int, s: int) -> int:
     outs = 1 if variant & GRAN else s
     bk = by
     return 4 * (by * (bk + 1) + bk * bx * outs)
+
+
+def valu2_lds(variant: int, bx: int, by: int, s: int, sy: int, bk: int) -> int:
+    outs, rows = (1, 1) if variant & GRAN else (s, sy)
+    return 4 * (by * rows * (bk + 1) + bk * bx * outs)
 
 
 def transpose_lds(variant: int, bx: int, by: int, s: int) -> int:
@@ -127,14 +138,20 @@ class InstanceData:
     def __init__(self, instances: List[dict]):
         self.by_key = {}
         for e in instances:
-            if e["family"] in (VALU, TRANSPOSE, MADD, JACOBI, POLYDIV):
+            if e["family"] == VALU2:
+                key = (VALU2, e["dtype"], e["variant"], e["bx"], e["by"], e["s"], e["sy"], e["bk"])
+            elif e["family"] in (VALU, TRANSPOSE, MADD, JACOBI, POLYDIV):
                 key = (e["family"], e["dtype"], e["variant"], e["bx"], e["by"], e["s"])
             else:
                 key = (MFMA, e["dtype"], e["variant"], e["bm"], e["bn"], e["bk"], e["wm"], e["wn"])
             self.by_key[key] = e
 
     def regs(self, family: int, dtype: int, variant: int, point: Tuple[int, ...]):
-        if family in (JACOBI, POLYDIV):
+        if family == VALU2:
+            bx, by, s, sy, bk = point
+            outs, rows = (1, 1) if variant & GRAN else (s, sy)
+            e = self.by_key.get((VALU2, dtype, 0, bx, by, outs, rows, bk))
+        elif family in (JACOBI, POLYDIV):
             b, s = point
             outs = 1 if variant & GRAN else s
             e = self.by_key.get((family, dtype, variant & NOLDS, b, 1, outs))
@@ -158,7 +175,7 @@ class InstanceData:
 def threads(family: int, point) -> int:
     if family in (JACOBI, POLYDIV):
         return point[0]
-    if family in (VALU, TRANSPOSE, MADD):
+    if family in (VALU, TRANSPOSE, MADD, VALU2):
         return point[0] * point[1]
     return 64 * point[3] * point[4]
 
@@ -166,6 +183,8 @@ def threads(family: int, point) -> int:
 def lds(family: int, dtype: int, variant: int, point) -> int:
     if family == VALU:
         return valu_lds(variant, *point)
+    if family == VALU2:
+        return valu2_lds(variant, *point)
     if family == TRANSPOSE:
         return transpose_lds(variant, *point)
     if family == MADD:
@@ -187,6 +206,8 @@ def fits(inst: InstanceData, family, dtype, variant, point, Z, V, T) -> bool:
 def variants(family: int):
     if family == MADD:
         return MADD_VARIANTS
+    if family == VALU2:
+        return VALU2_VARIANTS
     return MFMA_VARIANTS if family == MFMA else VALU_VARIANTS
 
 
@@ -246,6 +267,20 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
         def bits(applied):
             a = set(applied)
             return (GRAN if "gran" in a else 0) | (NOLDS if "nolds" in a else 0)
+
+        thr = co.parse_poly("bx*by")
+    elif family == VALU2:
+        program = ["bx", "by", "s", "sy", "bk"]
+        strategies = [co.Strategy("gran", False, frozenset({"r_Z", "r_V"}))]
+        names = {0: "rho_tiled", GRAN: "rho_tiled_s1"}
+
+        def lds_poly(applied):
+            if "gran" in applied:
+                return co.parse_poly("4*(by*(bk+1) + bk*bx)")
+            return co.parse_poly("4*(by*sy*(bk+1) + bk*bx*s)")
+
+        def bits(applied):
+            return GRAN if "gran" in applied else 0
 
         thr = co.parse_poly("bx*by")
     elif family == VALU:
