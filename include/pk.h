@@ -85,7 +85,8 @@ typedef struct {
 #define PK_FAMILY_MADD 3      /* matrix addition (Section 1, Fig. 1 and Fig. 2), f32 and i32 */
 #define PK_FAMILY_JACOBI 4    /* 1D Jacobi time step (Section 5, Fig. 6, Table 2), f32 and i32 */
 #define PK_FAMILY_POLYDIV 5   /* polynomial division mod P (Section 5, Fig. 8, Table 4), u32 residues */
-#define PK_NUM_FAMILIES 6
+#define PK_FAMILY_VALU2 6     /* the kernel of Section 2 with 2-D micro-tiles and a free LDS K extent, f32 and i32 */
+#define PK_NUM_FAMILIES 7
 
 /* Strategy bits of the VALU family (a variant is the set of strategies applied):
  * PK_VALU_GRAN  - granularity reduced to one output per thread (decision (3b), Section 5)
@@ -101,6 +102,7 @@ typedef struct {
 #define PK_MFMA_SINGLE 1
 #define PK_MFMA_GROUPED 2
 #define PK_MFMA_ELEMENT 4 /* internal: the twin of a program that reads rows element by element */
+#define PK_MFMA_MIXED 8   /* internal: a grouped kernel running a different tile program per product */
 
 /* A leaf choice together with its program parameters E.
  *   family  - PK_FAMILY_*
@@ -109,8 +111,22 @@ typedef struct {
  * VALU family: bx = threads along N (the paper's ub1), by = threads along M
  *   (the paper's B0), s = outputs per thread along N (the paper's s), bk =
  *   K extent of an LDS tile (the paper fixes it to B0; 0 means "= by").
+ * 2-D VALU family (PK_FAMILY_VALU2; Fig. 4's kernel generalised): bx x by
+ *   work-items, each computing s outputs along N (columns tx + w bx) and sy
+ *   along M (rows ty + v by), so a workgroup owns a (by sy) x (bx s) tile;
+ *   bk is the K extent of its LDS tiles, a parameter of its own (the paper
+ *   ties it to B0); LDS bytes e (by sy (bk + 1) + bk bx s); strategy bit
+ *   PK_VALU_GRAN (one output per work-item: s = sy = 1).
  * MFMA family: bm x bn output tile per workgroup, bk its K extent, wm x wn
- *   wavefronts of 64 lanes; unused fields are 0.
+ *   wavefronts of 64 lanes; unused fields are 0.  ks > 1 splits the product
+ *   along K into ks shares of about equal numbers of K steps, one workgroup
+ *   per tile and share: C is cleared first (unless accumulating) and each
+ *   share adds its sum to C with atomic float additions, so the order in
+ *   which the shares' sums enter C varies from run to run (the result stays
+ *   within the float32 bound; small-integer inputs stay exact).  ks is a
+ *   launch parameter, not a point of the case table: it changes no resource
+ *   counter (the same instance runs every ks).  Programs of more than 512
+ *   work-items are not split (PK_ERR_INVALID_ARG). 
  * Transposition family: bx = work-items along the columns of A (the paper's
  *   B1), by = work-items along its rows (B0), s = elements per work-item (s);
  *   a workgroup moves a (by * s) x bx tile of A.
@@ -144,6 +160,8 @@ typedef struct {
     int32_t variant;
     int32_t bx, by, s, bk;
     int32_t bm, bn, wm, wn;
+    int32_t ks;  /* MFMA family: shares of K the product is split into (0 or 1: none) */
+    int32_t sy;  /* 2-D VALU family: outputs per work-item along M (0 otherwise) */
 } pk_params;
 
 /* Selection policies for pk_select. */
@@ -272,25 +290,40 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
 
 /* ------------------------------------------------------------------ many products */
 /* A plan for G independent products C_g = [C_g +] A_g B_g (f32 or bf16 ->
- * f32), run as one persistent launch per tile configuration: every workgroup
- * strides over the configuration's tiles of all its products.  Sizes and
- * pointer arrays are host arrays (device pointers inside), all of length G;
- * products with M or N = 0 are skipped.  per_group_or_null gives each
- * product's MFMA leaf/parameters (resolved as in pk_matmul); NULL runs one
- * program for all products -- among the MFMA candidates with grouped
- * instances that fit every product, the one whose tiles cost the least
- * compute-unit time summed over the products under the CASE policy's model
- * (one launch; the latency of a single product does not count when the
- * products run side by side).  `policy` PK_POLICY_CASE or PK_POLICY_LEARNED
- * makes that choice; PK_POLICY_EXHAUSTIVE instead builds a plan of each
- * program that could run every product -- each point whose case-table leaf
- * holds for all of them, with each LDS-stage variant whose resources fit, as
- * a forced variant would run -- times it on the device (one untimed run,
- * median of three) and keeps the fastest; those runs write C, so it is
- * refused (PK_ERR_INVALID_ARG) together with accumulate.  Rows that are not
- * aligned for the 16-byte loads are read with element loads.  The plan copies its descriptors to the device when created
- * (allocating and synchronizing then); running it allocates nothing and does
- * not synchronize, so it may be captured in a HIP graph.  Pointers must stay
+ * f32), run as persistent launches: the workgroups of a launch stride over
+ * the tiles of all its products (the grid-stride loop of the paper's kernel,
+ * Section 2, Fig. 4, spanning many products).  Sizes and pointer arrays are
+ * host arrays (device pointers inside), all of length G; products with M or
+ * N = 0 are skipped, and K = 0 writes zeros (or leaves C with accumulate).
+ * Each product runs one MFMA program: a point of the case table whose leaf
+ * holds at the bound machine.  A mixed grouped kernel runs a different tile
+ * program per product in one launch (64x64, 128x64, 64x128 or 128x128
+ * output tiles of 2 x 2 wavefronts, one workgroup size, LDS sized for the
+ * largest); a plan is one launch whenever its products' programs are all one
+ * program or all programs of the mixed kernel with one LDS-stage count, and
+ * one launch per program otherwise.
+ * per_group_or_null gives each product's MFMA leaf/parameters (resolved as
+ * in pk_matmul).  With NULL, `policy`:
+ *   PK_POLICY_CASE        per product, the program of least estimated
+ *     compute-unit time at the residency of the kernel it runs in; the
+ *     kernel (each uniform program fitting every product, each mixed kernel)
+ *     of least summed estimate;
+ *   PK_POLICY_EXHAUSTIVE  the auto-tuning of Section 1 at plan level: a plan
+ *     of every uniform program and stage count, and of each mixed kernel
+ *     under three per-product rules (the CASE estimate, the largest tile
+ *     wasting at most 15 % or at most 35 % of its area on padding), each
+ *     timed on the device on the plan's own operands (one untimed run, the
+ *     median of three); the fastest is kept.  Those runs write C, so it is
+ *     refused (PK_ERR_INVALID_ARG) together with accumulate;
+ *   PK_POLICY_LEARNED     refused (PK_ERR_INVALID_ARG): the cost model
+ *     predicts the time of a single launch, not a product's share of a
+ *     persistent one.
+ * The tiles of a launch are ordered by estimated cost, most expensive first,
+ * and cut into 8 ranges of equal estimated cost, one per XCD.  Rows that are
+ * not aligned for the 16-byte loads are read with element loads.  The plan
+ * copies its descriptors to the device when created (allocating and
+ * synchronizing then); running it allocates nothing and does not
+ * synchronize, so it may be captured in a HIP graph.  Pointers must stay
  * valid while the plan is used.  Errors: PK_ERR_INVALID_ARG,
  * PK_ERR_UNSUPPORTED_DTYPE, PK_ERR_NO_FEASIBLE_BRANCH, PK_ERR_NOT_INSTANTIATED,
  * PK_ERR_HIP. */
@@ -309,6 +342,9 @@ int pk_grouped_plan_replay(const pk_grouped_plan *plan, void *hip_stream);
 /* Launch count, total tiles, and (cap >= G) the choice made per product. */
 int pk_grouped_plan_info(const pk_grouped_plan *plan, int32_t *launches, int64_t *total_tiles, pk_params *chosen,
                          int32_t cap);
+/* The kernel of launch i (0 <= i < launch count): *name points at a string
+ * the library owns (valid for the process).  Errors: PK_ERR_INVALID_ARG. */
+int pk_grouped_plan_kernel(const pk_grouped_plan *plan, int32_t i, const char **name);
 void pk_grouped_plan_destroy(pk_grouped_plan *plan);
 
 /* One-shot form: creates a plan (CASE choice when per_group_or_null is NULL),
@@ -417,20 +453,21 @@ int pk_instance_count(void);
 const char *pk_instance_name(int i);
 
 /* ------------------------------------------------------------------ cost model */
-/* The learned cost model: an 11-64-64-1 ReLU network predicting ln(seconds)
+/* The learned cost model: a 12-64-64-1 ReLU network predicting ln(seconds)
  * of a candidate launch from PK_NFEATURES features, trained on the device by
  * the library's own kernels (forward, backward, Adam) on timings from
  * pk_measure.  Not in the paper: it stands in for the auto-tuning the paper
  * leaves open for the program parameters (Section 1). */
-#define PK_NFEATURES 11
+#define PK_NFEATURES 12
 typedef struct pk_costmodel pk_costmodel; /* opaque */
 
 /* Features of candidate *p for C(MxN) = A(MxK) B(KxN) on the bound machine:
  * ln M, ln N, ln K, ln tile_m, ln tile_n, ln(outputs per work-item), LDS
  * bytes / 65536, estimated occupancy (resident wavefronts / maximum), tile
- * padding efficiency, wave quantisation efficiency, and `wide` (1 when the
- * operands' rows are aligned for the MFMA programs' 16-byte loads, 0 when they
- * run as their element-load twins; see pk_matmul).  out: PK_NFEATURES
+ * padding efficiency, wave quantisation efficiency (workgroups: tiles times
+ * the shares of K), `wide` (1 when the operands' rows are aligned for the
+ * MFMA programs' 16-byte loads, 0 when they run as their element-load twins;
+ * see pk_matmul), and ln of the shares of K (p->ks; 0 unsplit).  out: PK_NFEATURES
  * floats.  Errors as pk_launch_shape. */
 int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 float *out);
@@ -451,9 +488,9 @@ int pk_costmodel_train(const pk_table *tbl, const float *X, const float *seconds
 int pk_costmodel_predict(const pk_costmodel *cm, int device, const float *X, int64_t n, float *log_seconds);
 
 /* The network's raw forward/backward on the device: mean squared error of
- * the network with parameters `params` (host, 4993 floats in the order W1
+ * the network with parameters `params` (host, 5057 floats in the order W1
  * (64x11), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x 11, host) and
- * targets t (host); writes the gradient (4993 floats) and the loss.  Used to
+ * targets t (host); writes the gradient (5057 floats) and the loss.  Used to
  * check the kernels against a float64 reference. */
 int pk_costmodel_grad(int device, const float *params, const float *X, const float *t, int64_t n, float *grad,
                       float *loss);
@@ -462,7 +499,7 @@ int pk_costmodel_grad(int device, const float *params, const float *X, const flo
  * place; step >= 1 is the step number used for bias correction). */
 int pk_costmodel_adam_step(int device, float *params, const float *grad, float *m, float *v, int64_t step, float lr);
 
-/* Parameter export (*n = 4993; out may be NULL to query), text save/load
+/* Parameter export (*n = 5057; out may be NULL to query), text save/load
  * (the file carries the standardisation, the machine and the element type
  * it was trained on; a file without a dtype line is float32), release, and
  * the machine fingerprint string. */

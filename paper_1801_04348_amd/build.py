@@ -39,20 +39,27 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE,
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
 HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp",
                 "madd.cpp", "jacobi.cpp"]
-DEVICE_SOURCES = ["costmodel.hip", "polydiv.hip", "probes.hip"]
+DEVICE_SOURCES = ["costmodel.hip", "polydiv.hip", "probes.hip", "fill.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}
 DT_CTYPE = {F32: "float", I32: "int32_t"}
-FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA, FAM_PD = 0, 1, 2, 3, 4, 5
+FAM_VALU, FAM_MFMA, FAM_TR, FAM_MA, FAM_JA, FAM_PD, FAM_VALU2 = 0, 1, 2, 3, 4, 5, 6
 VALU_GRAN, VALU_NOLDS = 1, 2
 MFMA_SINGLE = 1
 MFMA_GROUPED = 2
 MFMA_ELEMENT = 4
+MFMA_MIXED = 8
+# the mixed grouped kernels' tile programs (csrc/kernels/kargs.hpp kMixedTile,
+# in the same order) and K tiles
+MIXED_TILES = [(64, 64), (128, 64), (64, 128), (128, 128)]
+MIXED_BK = {0: 32, 2: 64}
 
 # program-parameter domains (the families' point sets)
 VALU_B = (4, 8, 16, 32)
 VALU_S = (1, 2, 4, 8)
+VALU2_S = (2, 4)      # outputs per work-item along N and along M
+VALU2_BK = (16, 32)   # K extent of the LDS tiles
 JA_B = (16, 32, 64, 128, 256, 512, 1024)
 JA_S = (1, 2, 4, 8)
 MA_BX = (64, 128, 256)
@@ -70,6 +77,10 @@ MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128,
 
 def valu_lds(bx, by, s, nolds):
     return 0 if nolds else 4 * (by * (by + 1) + by * bx * s)
+
+
+def valu2_lds(bx, by, sx, sy, bk):
+    return 4 * (by * sy * (bk + 1) + bk * bx * sx)
 
 
 def mfma_reg_cap(dt, threads, stages, kind, bm=0, bn=0):
@@ -110,6 +121,21 @@ def instances():
                                      bx=bx, by=by, s=s, bk=by, bm=0, bn=0, wm=0, wn=0, threads=bx * by,
                                      lds=valu_lds(bx, by, s, nolds), tile_m=by, tile_n=bx * s)
                         out.append(("valu_%s_by%d" % (DT_NAME[dt], by), name, body, entry))
+    # 2-D micro-tile VALU programs: workgroups of one to four wavefronts; the
+    # one-output program of each workgroup and K extent (granularity reduction)
+    for dt in (F32, I32):
+        for bx in VALU_B:
+            for by in VALU_B:
+                if not 64 <= bx * by <= 256:
+                    continue
+                for bk in VALU2_BK:
+                    for sx, sy in [(1, 1)] + [(a, b) for a in VALU2_S for b in VALU2_S]:
+                        name = "pk_valu2_%s_bx%d_by%d_s%dx%d_bk%d" % (DT_NAME[dt], bx, by, sy, sx, bk)
+                        body = "pkk::valu_tiled2<%s, %d, %d, %d, %d, %d>(a);" % (DT_CTYPE[dt], bx, by, sx, sy, bk)
+                        entry = dict(family=FAM_VALU2, variant=0, dtype=dt, bx=bx, by=by, s=sx, sy=sy, bk=bk, bm=0,
+                                     bn=0, wm=0, wn=0, threads=bx * by, lds=valu2_lds(bx, by, sx, sy, bk),
+                                     tile_m=by * sy, tile_n=bx * sx)
+                        out.append(("valu2_%s_bx%d" % (DT_NAME[dt], bx), name, body, entry))
     for dt, cfgs, fn in ((F32, MFMA_F32, "mfma_f32"), (BF16, MFMA_BF16, "mfma_bf16")):
         for (bm, bn, bk, wm, wn) in cfgs:
             for stages in (2, 1):
@@ -205,6 +231,8 @@ def instances():
             if bm > 128 or bn > 128:
                 continue
             for stages in (2, 1):
+                if dt == BF16 and bm * bn >= 128 * 128 and stages == 2:
+                    continue  # would spill at 256 registers a lane (its loads at chosen addresses hold more)
                 name = "pk_grouped_%s_%dx%dx%d_w%dx%d_st%d" % (DT_NAME[dt], bm, bn, bk, wm, wn, stages)
                 body = "pkk::%s<%d, %d, %d, %d, %d, %d>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages)
                 entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE),
@@ -212,13 +240,28 @@ def instances():
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
                              attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "grouped"))
                 out.append(("grouped_%s" % DT_NAME[dt], name, body, entry))
+    # mixed grouped kernels: a tile program per product (kMixedTile), 2 x 2
+    # wavefronts, LDS sized for the largest program
+    for dt, fn in ((F32, "grouped_mixed_f32"), (BF16, "grouped_mixed_bf16")):
+        bk = MIXED_BK[dt]
+        bm, bn = max(MIXED_TILES, key=lambda t: t[0] * t[1])
+        for stages in ((2, 1) if dt == F32 else (1,)):  # bf16: its 128 x 128 program spills with two stages
+            name = "pk_grouped_mixed_%s_w2x2_st%d" % (DT_NAME[dt], stages)
+            body = "pkk::%s<%d>(g);" % (fn, stages)
+            lds = max(mfma_lds(dt, m, n, bk, stages) for m, n in MIXED_TILES)
+            entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | MFMA_MIXED | (0 if stages == 2 else MFMA_SINGLE),
+                         dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=2, wn=2, threads=256, lds=lds,
+                         tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
+                         attrs=mfma_reg_cap(dt, 256, stages, "grouped"))
+            out.append(("grouped_mixed_%s" % DT_NAME[dt], name, body, entry))
     return out
 
 
 def _entry_c(name, e):
-    return ('    {"%s", (const void *)&%s, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d},'
+    return ('    {"%s", (const void *)&%s, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d},'
             % (name, name, e["family"], e["variant"], e["dtype"], e["bx"], e["by"], e["s"], e["bk"],
-               e["bm"], e["bn"], e["wm"], e["wn"], e["threads"], e["lds"], e["tile_m"], e["tile_n"]))
+               e["bm"], e["bn"], e["wm"], e["wn"], e["threads"], e["lds"], e["tile_m"], e["tile_n"],
+               e.get("sy", 0)))
 
 
 def generate():

@@ -12,7 +12,7 @@ types).
 
 eval: for every shape of a held-out store, the LEARNED choice as pk_select
 makes it -- the candidate with the least predicted time, except that when the
-best two predictions are within 10 % every candidate predicted within 10 % of
+best two predictions are within 5 % every candidate predicted within 5 % of
 the best is measured and the fastest kept; the measurement used is the
 store's own -- and the CASE choice, each scored by its measured time against
 the best measured candidate:  ratio = t_best / t_pick = GF_pick / GF_best.
@@ -34,7 +34,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-MARGIN = 0.10
+MARGIN = 0.05
 
 
 def load_store(paths, fingerprint):

@@ -65,6 +65,11 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
     }
     const KernelEntry *e = find_instance(pin->family, variant, dtype, pt);
     if (!e) return fail(PK_ERR_NOT_INSTANTIATED, "no compiled instance for these parameters");
+    if (pin->ks < 0 || pin->ks > kMaxSplits ||
+        (pin->ks > 1 && (pin->family != PK_FAMILY_MFMA || e->threads > pkk::kSplittableThreads)))
+        return fail(PK_ERR_INVALID_ARG, "ks: shares of K are 0 or 1 (none), or up to " + std::to_string(kMaxSplits) +
+                                            " for MFMA programs of up to " +
+                                            std::to_string(pkk::kSplittableThreads) + " work-items");
     *pout = *pin;
     point_params(pin->family, pt, pout);
     pout->leaf = leaf;
@@ -160,10 +165,15 @@ int launch(const pk_machine &m, const KernelEntry &e0, const MmArgs &args, hipSt
         if (!pe) return fail(PK_ERR_NOT_INSTANTIATED, std::string("no element-load twin of ") + e0.name);
     }
     const KernelEntry &e = *pe;
-    const int64_t grid = launch_grid(m, e, args.M, args.N);
+    MmArgs a = args;
+    if (e.family != PK_FAMILY_MFMA || a.K <= 0 || a.splits < 2) a.splits = 0;
+    const int64_t grid = launch_grid(m, e, args.M, args.N) * std::max(a.splits, 1);
     if (grid <= 0) return PK_OK;
     if (grid > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "grid too large");
-    MmArgs a = args;
+    if (a.splits > 1 && !a.accumulate) {  // the shares add into C: clear it first
+        int rc = zero_matrix(m, a.C, a.ldc, a.M, a.N, stream);
+        if (rc != PK_OK) return rc;
+    }
     void *kargs[] = {&a};
     hipError_t err = hipLaunchKernel(e.fn, dim3((unsigned)grid), dim3((unsigned)e.threads), kargs, 0, stream);
     if (err != hipSuccess)
@@ -323,6 +333,7 @@ int pk_case_table_describe(const pk_table *tbl, char *out, size_t cap, size_t *n
         const KernelResources *r = resources_of(e.name);
         o << (i ? "," : "") << "{\"name\":\"" << e.name << "\",\"family\":" << e.family << ",\"variant\":" << e.variant
           << ",\"dtype\":" << e.dtype << ",\"bx\":" << e.bx << ",\"by\":" << e.by << ",\"s\":" << e.s
+          << ",\"sy\":" << e.sy
           << ",\"bk\":" << e.bk << ",\"bm\":" << e.bm << ",\"bn\":" << e.bn << ",\"wm\":" << e.wm << ",\"wn\":" << e.wn
           << ",\"threads\":" << e.threads << ",\"lds_bytes\":" << e.lds_bytes << ",\"tile_m\":" << e.tile_m
           << ",\"tile_n\":" << e.tile_n;
@@ -425,13 +436,13 @@ int pk_estimate(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t
                 double *seconds) {
     if (!tbl || !p || !seconds) return fail(PK_ERR_INVALID_ARG, "null argument");
     if (M < 0 || N < 0 || K < 0) return fail(PK_ERR_INVALID_ARG, "negative dimension");
-    if (p->family != PK_FAMILY_VALU && p->family != PK_FAMILY_MFMA)
+    if (p->family != PK_FAMILY_VALU && p->family != PK_FAMILY_VALU2 && p->family != PK_FAMILY_MFMA)
         return fail(PK_ERR_INVALID_ARG, "estimates cover the matmul families");
     pk_params q;
     const KernelEntry *e = nullptr;
     int rc = resolve(tbl, p, (int)dtype, &q, &e);
     if (rc != PK_OK) return rc;
-    *seconds = estimate_seconds(tbl->machine, *e, (int)dtype, M, N, K, wide != 0);
+    *seconds = estimate_seconds(tbl->machine, *e, (int)dtype, M, N, K, wide != 0, std::max(q.ks, 1));
     return PK_OK;
 }
 
@@ -448,7 +459,7 @@ int pk_launch_shape(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int
         int rc = resolve(tbl, p, (int)dtype, &q, &e);
         if (rc != PK_OK) return rc;
     }
-    if (grid) *grid = grid_of(tbl->machine, *e, M, N);
+    if (grid) *grid = grid_of(tbl->machine, *e, M, N) * (e->family == PK_FAMILY_MFMA ? std::max(q.ks, 1) : 1);
     if (block) *block = e->threads;
     if (lds_bytes) *lds_bytes = e->lds_bytes;
     return PK_OK;
@@ -471,7 +482,8 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
             if (rc != PK_OK) return rc;
             params_or_null = &sel;
         }
-        if (params_or_null->family != PK_FAMILY_VALU && params_or_null->family != PK_FAMILY_MFMA)
+        if (params_or_null->family != PK_FAMILY_VALU && params_or_null->family != PK_FAMILY_VALU2 &&
+            params_or_null->family != PK_FAMILY_MFMA)
             return fail(PK_ERR_INVALID_ARG, "parameters of a family that is not a product");
         pk_params q;
         const KernelEntry *e = nullptr;
@@ -488,7 +500,8 @@ int pk_matmul(const pk_table *tbl, const pk_params *params_or_null, pk_dtype dty
             rc = resolve(tbl, &sel, (int)dtype, &q, &e);
             if (rc != PK_OK) return rc;
         }
-        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0, wide ? 1 : 0};
+        MmArgs args{A, B, C, lda, ldb, ldc, (int32_t)M, (int32_t)N, (int32_t)K, accumulate ? 1 : 0, wide ? 1 : 0,
+                    q.ks, 0};
         return launch(tbl->machine, *e, args, (hipStream_t)hip_stream);
     } catch (const std::exception &ex) {
         return fail(PK_ERR_INVALID_ARG, ex.what());

@@ -23,6 +23,15 @@
 // The register-pressure strategy (1) of the experiments has no counterpart:
 // the compiler already fits each instance's registers to its launch bounds.
 //
+// 2-D VALU family (Fig. 4's kernel generalised): program parameters bx, by,
+// s (outputs per work-item along N), sy (along M) and bk, the K extent of the
+// LDS tiles, free of by; a workgroup owns a (by sy) x (bx s) tile.  LDS bytes
+// e (by sy (bk + 1) + bk bx s).  Strategy, omega order:
+//   gran  (source; sigma = {r_Z, r_V}) one output per work-item (s = sy = 1)
+// The domain holds the 2-D points only (s, sy in {2, 4}, workgroups of one to
+// four wavefronts, bk in {16, 32}); one output per work-item in both
+// directions is the VALU family's program.
+//
 // Transposition family (Section 5.2, Fig. 7): program parameters bx (the
 // paper's B1, work-items along the columns of A), by (B0), s (elements per
 // work-item); strategies gran and nolds as in the VALU family.  LDS bytes of
@@ -64,6 +73,10 @@ struct MfmaPoint {
 // Program-parameter domains.  VALU: {4, 8, 16, 32}^2 x {1, 2, 4, 8}.
 const int kValuB[] = {4, 8, 16, 32};
 const int kValuS[] = {1, 2, 4, 8};
+
+// 2-D VALU: (bx, by) with one to four wavefronts, s and sy in {2, 4}, bk in {16, 32}
+const int kValu2S[] = {2, 4};
+const int kValu2Bk[] = {16, 32};
 
 const int kMaBx[] = {64, 128, 256};
 const int kMaBy[] = {1, 2, 4};
@@ -174,6 +187,37 @@ Family matmul_family(int family, int dtype) {
             if (sym == rho_t1 || sym == rho_d1) variant |= PK_VALU_GRAN;
             if (sym == rho_d || sym == rho_d1) variant |= PK_VALU_NOLDS;
             return table_regs(PK_FAMILY_VALU, variant, dtype, pt, 64);
+        };
+        return f;
+    }
+    if (family == PK_FAMILY_VALU2) {
+        if (dtype != PK_F32 && dtype != PK_I32) throw std::runtime_error("2-D VALU family: f32 and i32 only");
+        const int bx = add_sym(f, "bx", SYM_PROGRAM), by = add_sym(f, "by", SYM_PROGRAM),
+                  s = add_sym(f, "s", SYM_PROGRAM), sy = add_sym(f, "sy", SYM_PROGRAM),
+                  bk = add_sym(f, "bk", SYM_PROGRAM);
+        const int rho_t = add_sym(f, "rho_tiled", SYM_TABLE), rho_t1 = add_sym(f, "rho_tiled_s1", SYM_TABLE);
+        const int64_t es = 4;
+        f.point_syms = {bx, by, s, sy, bk};
+        for (int x : kValuB)
+            for (int y : kValuB) {
+                if (x * y < 64 || x * y > 256) continue;
+                for (int z : kValu2S)
+                    for (int zy : kValu2S)
+                        for (int k : kValu2Bk) f.points.push_back({x, y, z, zy, k});
+            }
+        // LDS bytes: A tile (by sy) x (bk + 1) and B tile bk x (bx s)
+        const Poly lds_full = P(es) * (S(by) * S(sy) * (S(bk) + P(1)) + S(bk) * S(bx) * S(s));
+        const Poly lds_g1 = P(es) * (S(by) * (S(bk) + P(1)) + S(bk) * S(bx));
+        CounterDef rz{"r_Z", false, m.Z, nullptr};
+        rz.value = [=](uint32_t ap) { return (ap & PK_VALU_GRAN) ? lds_g1 : lds_full; };
+        CounterDef rv{"r_V", false, m.V, nullptr};
+        rv.value = [=](uint32_t ap) { return S((ap & PK_VALU_GRAN) ? rho_t1 : rho_t); };
+        CounterDef rt{"r_T", false, m.T, nullptr};
+        rt.value = [=](uint32_t) { return S(bx) * S(by); };
+        f.counters = {rz, rv, rt};
+        f.strategies = {StrategyDef{"gran", false, 0b011u}};
+        f.table = [=](int sym, const std::vector<int64_t> &pt) -> int64_t {
+            return table_regs(PK_FAMILY_VALU2, sym == rho_t1 ? PK_VALU_GRAN : 0, dtype, pt, 64);
         };
         return f;
     }
@@ -310,7 +354,12 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
     }
     if (family == PK_FAMILY_VALU) {
         if (p.bk != 0 && p.bk != p.by) return false;  // the paper's K tile: bk = by
+        if (p.sy > 1) return false;                     // one output row per work-item
         *pt = {p.bx, p.by, p.s};
+        return true;
+    }
+    if (family == PK_FAMILY_VALU2) {
+        *pt = {p.bx, p.by, p.s, p.sy, p.bk};
         return true;
     }
     if (family == PK_FAMILY_MFMA) {
@@ -322,7 +371,15 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
-    p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = 0;
+    p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = p->sy = 0;
+    if (family == PK_FAMILY_VALU2) {
+        p->bx = (int32_t)pt[0];
+        p->by = (int32_t)pt[1];
+        p->s = (int32_t)pt[2];
+        p->sy = (int32_t)pt[3];
+        p->bk = (int32_t)pt[4];
+        return;
+    }
     if (family == PK_FAMILY_JACOBI || family == PK_FAMILY_POLYDIV) {
         p->bx = (int32_t)pt[0];
         p->by = 1;
@@ -372,6 +429,16 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
         for (const auto &e : registry())
             if (e.family == family && e.dtype == dtype && e.variant == (variant & PK_VALU_NOLDS) && e.bx == pt[0] &&
                 e.s == s)
+                return &e;
+        return nullptr;
+    }
+    if (family == PK_FAMILY_VALU2) {
+        // granularity reduction runs the one-output program of the same
+        // workgroup and K extent
+        const int64_t sx = (variant & PK_VALU_GRAN) ? 1 : pt[2], sy = (variant & PK_VALU_GRAN) ? 1 : pt[3];
+        for (const auto &e : registry())
+            if (e.family == family && e.dtype == dtype && e.variant == 0 && e.bx == pt[0] && e.by == pt[1] &&
+                e.s == sx && e.sy == sy && e.bk == pt[4])
                 return &e;
         return nullptr;
     }

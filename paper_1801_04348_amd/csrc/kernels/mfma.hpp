@@ -22,13 +22,15 @@
 // so a lane's operands are contiguous in LDS.  The set of products summed is
 // unchanged.
 //
-// Global loads are 16 bytes wide, so the leading dimensions must keep rows
-// 16-byte aligned (lda, ldb multiples of 4 floats / 8 bfloat16 and 16-byte
-// aligned bases); the host checks this.  Tiles crossing the matrix edge clamp
-// the rows of A and the columns of B they read to the last one in range
-// (results outside C are never stored), read k beyond K from a block of zeros,
-// and guard their stores.  Edge loads choose an address, never a loaded value,
-// so they carry no branches and stay in flight together.
+// Global loads are 16 bytes wide (4 bytes for the column pairs of a bfloat16
+// B), so the leading dimensions must keep rows aligned (lda, ldb multiples of
+// 4 floats / 8 bfloat16 and 16-byte aligned bases); the host checks this and
+// otherwise launches the element-load twin.  Tiles crossing the matrix edge
+// keep the wide loads: they clamp the rows of A and the column chunks of B
+// they read to the last chunk in range (results outside C are never stored),
+// zero the elements of A at k >= K, read the rows of B at k >= K from a block
+// of zeros, and guard their stores.  Edge loads choose an address, never a
+// loaded value, so they carry no branches and stay in flight together.
 //
 // Workgroup -> tile map: workgroups are dispatched round-robin over the 8 XCDs
 // (each with its own L2); blocks b and b+8 land on the same XCD, so the map
@@ -59,7 +61,7 @@ template <class T> using gmut = __attribute__((address_space(1))) T *;
 // the source of every element at k >= K (read only)
 static __device__ __attribute__((aligned(16))) unsigned int kZeroBlock[4] = {0u, 0u, 0u, 0u};
 
-constexpr int XCDS = 8;
+constexpr int XCDS = kXcds;
 constexpr int GROUP_M = 8;
 
 // tile (tm, tn) of linear workgroup b among tiles_m x tiles_n
@@ -78,24 +80,38 @@ __device__ __forceinline__ void tile_of(int64_t b, int tiles_m, int tiles_n, int
 }
 
 // ------------------------------------------------------------------ float32
-// One BM x BN output tile at (row0, col0).  `vec`: the rows of A and B are
-// 16-byte aligned, so interior tiles may use 16-byte loads.  The caller
-// synchronises the workgroup before reusing the LDS for another tile.
+// LDS floats of a float32 tile program: STAGES x (A tile BM x (BK + 4)),
+// then STAGES x (B tile BK x (BN + 4)); every part starts 16-byte aligned.
+template <int BM, int BN, int BK, int STAGES> struct F32Lds {
+    static constexpr int LDA_S = BK + 4, LDB_S = BN + 4;
+    static constexpr int A = BM * LDA_S, B = BK * LDB_S;
+    static constexpr int floats = STAGES * (A + B);
+};
+
+// One BM x BN output tile at (row0, col0) over the K steps [kt0, kt1) (of
+// BK each), its LDS tiles at `lds` (F32Lds::floats floats).  `vec`: the rows
+// of A and B are 16-byte aligned, so interior tiles may use 16-byte loads.
+// With a.splits > 1 the tile's sum over its K steps is added to C atomically
+// (C holds zeros or the sums of the other shares of K); otherwise it is
+// stored (added to C with a.accumulate).  The caller synchronises the
+// workgroup before reusing the LDS for another tile.
+
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
-__device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
+__device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, const int col0, const bool vec,
+                                              float *lds, const int kt0, const int kt1) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
-    constexpr int PA = 4, PB = 4;
-    constexpr int LDA_S = BK + PA, LDB_S = BN + PB;
+    using L = F32Lds<BM, BN, BK, STAGES>;
+    constexpr int LDA_S = L::LDA_S, LDB_S = L::LDB_S;
     constexpr int A4 = BM * BK / 4 / NT;  // float4 loads per work-item per A tile
     constexpr int B4 = BK * BN / 4 / NT;
     static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
     static_assert(A4 >= 1 && B4 >= 1 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tile loads");
     static_assert(BK % 8 == 0, "BK");
 
-    __shared__ __attribute__((aligned(16))) float As[STAGES][BM * LDA_S];
-    __shared__ __attribute__((aligned(16))) float Bs[STAGES][BK * LDB_S];
+    float *const As0 = lds;                 // stage st: As0 + st * L::A
+    float *const Bs0 = lds + STAGES * L::A;  // stage st: Bs0 + st * L::B
 
     const gptr<float> __restrict__ A = (gptr<float>)a.A;
     const gptr<float> __restrict__ B = (gptr<float>)a.B;
@@ -134,11 +150,19 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             rb[u] = *reinterpret_cast<gptr<f32x4>>(B + (int64_t)(k0 + rr) * a.ldb + col0 + c4);
         }
     };
-    // Any K step, edge tiles included.  EDGE_ADDR: every load goes to a chosen
-    // address (the wide/narrow choices are uniform across the workgroup), for
-    // programs whose steps are mostly edge steps (element loads, many small
-    // products); otherwise guarded loads, which hold fewer registers where
-    // edge steps are rare.
+    // Any K step, edge tiles included.  Without EDGE_ADDR: guarded loads
+    // (16 bytes where the chunk is wholly inside the matrix, else element by
+    // element), which hold fewer registers where edge steps are rare.
+    // EDGE_ADDR, for programs whose steps are mostly edge steps (many small
+    // products): every load goes to a chosen address.  Aligned rows (vec):
+    // 16-byte loads at addresses clamped into the matrix.
+    // Rows of A past M read row M - 1 and columns of B past N read the chunk
+    // holding column N - 1 (their results are never stored); in a step past
+    // the end of K, A's chunks past k = K - 1 read the chunk holding it and
+    // the elements at k >= K become zeros, and the rows of B at k >= K read a
+    // block of zeros.  Every chunk read holds an element of the matrix, so it
+    // lies inside its aligned row.
+    // Unaligned rows: element loads.
     auto gload = [&](int k0) {
         if constexpr (!EDGE_ADDR) {
             const bool kfull = (k0 + BK <= K);
@@ -171,44 +195,56 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             return;
         }
         const gptr<float> zero = (gptr<float>)(const void *)kZeroBlock;
-        if (vec && k0 + BK <= K) {
+        if (vec) {
+            const int klast = (K - 1) & ~3, nlast = (N - 1) & ~3;
+            if (k0 + BK <= K) {
 #pragma unroll
-            for (int u = 0; u < A4; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
-                ra[u] = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c4);
-            }
-        } else {
+                for (int u = 0; u < A4; ++u) {
+                    const int f = tid + u * NT;
+                    const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+                    ra[u] = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c4);
+                }
+            } else {
 #pragma unroll
-            for (int u = 0; u < A4; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
-                const gptr<float> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
+                for (int u = 0; u < A4; ++u) {
+                    const int f = tid + u * NT;
+                    const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+                    const int k = k0 + c4;
+                    f32x4 v = *reinterpret_cast<gptr<f32x4>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda +
+                                                             min(k, klast));
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = k0 + c4 + e;
-                    ra[u][e] = *(k < K ? row + k : zero);
+                    for (int e = 0; e < 4; ++e) v[e] = k + e < K ? v[e] : 0.0f;
+                    ra[u] = v;
                 }
             }
+#pragma unroll
+            for (int u = 0; u < B4; ++u) {
+                const int f = tid + u * NT;
+                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+                const int k = k0 + rr;
+                rb[u] = *reinterpret_cast<gptr<f32x4>>(k < K ? B + (int64_t)k * a.ldb + min(col0 + c4, nlast) : zero);
+            }
+            return;
         }
-        if (vec && col0 + BN <= N) {
 #pragma unroll
-            for (int u = 0; u < B4; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
-                const int k = k0 + rr;
-                rb[u] = *reinterpret_cast<gptr<f32x4>>(k < K ? B + (int64_t)k * a.ldb + col0 + c4 : zero);
+        for (int u = 0; u < A4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
+            const gptr<float> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + c4 + e;
+                ra[u][e] = *(k < K ? row + k : zero);
             }
-        } else {
+        }
 #pragma unroll
-            for (int u = 0; u < B4; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
-                const int k = k0 + rr;
-                const gptr<float> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
+        for (int u = 0; u < B4; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
+            const int k = k0 + rr;
+            const gptr<float> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) rb[u][e] = *(row ? row + min(col0 + c4 + e, N - 1) : zero);
-            }
+            for (int e = 0; e < 4; ++e) rb[u][e] = *(row ? row + min(col0 + c4 + e, N - 1) : zero);
         }
     };
     auto sstore = [&](int st) {
@@ -216,18 +252,18 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         for (int u = 0; u < A4; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 4), c4 = (f % (BK / 4)) * 4;
-            *reinterpret_cast<f32x4 *>(&As[st][rr * LDA_S + c4]) = ra[u];
+            *reinterpret_cast<f32x4 *>(&As0[st * L::A + rr * LDA_S + c4]) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < B4; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BN / 4), c4 = (f % (BN / 4)) * 4;
-            *reinterpret_cast<f32x4 *>(&Bs[st][rr * LDB_S + c4]) = rb[u];
+            *reinterpret_cast<f32x4 *>(&Bs0[st * L::B + rr * LDB_S + c4]) = rb[u];
         }
     };
     auto compute = [&](int st) {
-        const float *as = &As[st][(wm * WTM + r) * LDA_S + h * (BK / 2)];
-        const float *bs = &Bs[st][(h * (BK / 2)) * LDB_S + wn * WTN + r];
+        const float *as = &As0[st * L::A + (wm * WTM + r) * LDA_S + h * (BK / 2)];
+        const float *bs = &Bs0[st * L::B + (h * (BK / 2)) * LDB_S + wn * WTN + r];
 #pragma unroll
         for (int kc = 0; kc < BK / 2; kc += 4) {
             f32x4 af[TM];
@@ -248,38 +284,38 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         }
     };
 
-    const int KT = (K + BK - 1) / BK;
-    // leading K steps that need no guards: all of them for an interior tile
-    // on aligned rows, except a partial last one
-    const int KF = (vec && interior) ? K / BK : 0;
+    // the K steps [kt0, kt1) of this workgroup: all of K, or its share of a
+    // product split along K.  Leading steps that need no guards: all of them
+    // for an interior tile on aligned rows, except a partial last one.
+    const int KF = (vec && interior) ? max(kt0, min(K / BK, kt1)) : kt0;
     if (STAGES == 2) {
-        if (KT > 0) {
-            if (KF > 0)
-                gload_fast(0);
+        if (kt1 > kt0) {
+            if (KF > kt0)
+                gload_fast(kt0 * BK);
             else
-                gload(0);
+                gload(kt0 * BK);
             sstore(0);
         }
         __syncthreads();
-        int kt = 0;
+        int kt = kt0;
         // steps whose successor is unguarded too: a loop without branches, so
         // the next step's loads stay in flight while this step multiplies
         for (; kt + 1 < KF; ++kt) {
-            const int cur = kt & 1;
+            const int cur = (kt - kt0) & 1;
             gload_fast((kt + 1) * BK);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
         }
-        for (; kt < KT; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < KT) gload((kt + 1) * BK);
+        for (; kt < kt1; ++kt) {
+            const int cur = (kt - kt0) & 1;
+            if (kt + 1 < kt1) gload((kt + 1) * BK);
             compute(cur);
-            if (kt + 1 < KT) sstore(cur ^ 1);
+            if (kt + 1 < kt1) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
-        int kt = 0;
+        int kt = kt0;
         for (; kt < KF; ++kt) {
             gload_fast(kt * BK);
             __syncthreads();
@@ -287,7 +323,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             __syncthreads();
             compute(0);
         }
-        for (; kt < KT; ++kt) {
+        for (; kt < kt1; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
@@ -307,29 +343,42 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
                 const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
                 if (interior || (gr < M && gc < N)) {
                     const gmut<float> p = C + (int64_t)gr * a.ldc + gc;
-                    *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
+                    if (a.splits > 1)  // a share of K: added to C, which holds the other shares' sums
+                        unsafeAtomicAdd((float *)p, acc[i][j][v]);
+                    else
+                        *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
                 }
             }
         }
 }
 
 // ------------------------------------------------------------------ bfloat16
-// bfloat16 tile; `vec`: A rows 16-byte aligned and B rows 4-byte aligned.
+// LDS elements (16-bit) of a bfloat16 tile program: STAGES x (A tile BM x
+// (BK + 8)), then STAGES x (B transposed, BN x (BK + 8)).
+template <int BM, int BN, int BK, int STAGES> struct Bf16Lds {
+    static constexpr int LD_S = BK + 8;
+    static constexpr int A = BM * LD_S, B = BN * LD_S;
+    static constexpr int elems = STAGES * (A + B);
+};
+
+// bfloat16 tile, its LDS tiles at `lds` (Bf16Lds::elems elements); `vec`: A
+// rows 16-byte aligned and B rows 4-byte aligned.
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
-__device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec) {
+__device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec,
+                                               unsigned short *lds, const int kt0, const int kt1) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
-    constexpr int P = 8;
-    constexpr int LD_S = BK + P;                 // row stride (elements) of As and Bt
+    using L = Bf16Lds<BM, BN, BK, STAGES>;
+    constexpr int LD_S = L::LD_S;                // row stride (elements) of As and Bt
     constexpr int A8 = BM * BK / 8 / NT;         // 16-byte loads per work-item per A tile
     constexpr int B8 = (BK / 8) * (BN / 2) / NT; // (8 k rows x 2 columns) blocks per work-item
     static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
     static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && ((BK / 8) * (BN / 2)) % NT == 0, "tile loads");
     static_assert(BK % 32 == 0, "BK");
 
-    __shared__ __attribute__((aligned(16))) unsigned short As[STAGES][BM * LD_S];
-    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES][BN * LD_S];
+    unsigned short *const As0 = lds;                 // stage st: As0 + st * L::A
+    unsigned short *const Bt0 = lds + STAGES * L::A;  // stage st: Bt0 + st * L::B
 
     const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A;
     const gptr<unsigned short> __restrict__ B = (gptr<unsigned short>)a.B;
@@ -368,7 +417,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
                 rb[u][e] = *reinterpret_cast<gptr<unsigned int>>(B + (int64_t)(k0 + kr + e) * a.ldb + col0 + cp);
         }
     };
-    auto gload = [&](int k0) {  // any K step: as in the float32 tile
+    auto gload = [&](int k0) {  // any K step: as in the float32 tile (chunks of 8 k, column pairs of B)
         if constexpr (!EDGE_ADDR) {
             const bool kfull = (k0 + BK <= K);
 #pragma unroll
@@ -403,53 +452,67 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             }
             return;
         }
-        if (vec && k0 + BK <= K) {
+        const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
+        if (vec) {
+            const int klast = (K - 1) & ~7, nlast = (N - 1) & ~1;
+            if (k0 + BK <= K) {
 #pragma unroll
-            for (int u = 0; u < A8; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
-                ra[u] = *reinterpret_cast<gptr<u16x8>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c8);
-            }
-        } else {
-            const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
+                for (int u = 0; u < A8; ++u) {
+                    const int f = tid + u * NT;
+                    const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+                    ra[u] = *reinterpret_cast<gptr<u16x8>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda + k0 + c8);
+                }
+            } else {
 #pragma unroll
-            for (int u = 0; u < A8; ++u) {
-                const int f = tid + u * NT;
-                const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
-                const gptr<unsigned short> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
+                for (int u = 0; u < A8; ++u) {
+                    const int f = tid + u * NT;
+                    const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+                    const int k = k0 + c8;
+                    u32x4 v = *reinterpret_cast<gptr<u32x4>>(A + (int64_t)min(row0 + rr, M - 1) * a.lda +
+                                                             min(k, klast));
+                    // word w holds k + 2w (low half) and k + 2w + 1 (high half)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = k0 + c8 + e;
-                    ra[u][e] = *(k < K ? row + k : zero);
+                    for (int w = 0; w < 4; ++w)
+                        v[w] &= k + 2 * w + 1 < K ? 0xffffffffu : (k + 2 * w < K ? 0x0000ffffu : 0u);
+                    ra[u] = __builtin_bit_cast(u16x8, v);
                 }
             }
-        }
-        if (vec && col0 + BN <= N) {
 #pragma unroll
             for (int u = 0; u < B8; ++u) {
                 const int f = tid + u * NT;
                 const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;  // column pair, first k row
+                const int c = min(col0 + cp, nlast);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int k = k0 + kr + e;
-                    rb[u][e] = *(k < K ? reinterpret_cast<gptr<unsigned int>>(B + (int64_t)k * a.ldb + col0 + cp)
+                    rb[u][e] = *(k < K ? reinterpret_cast<gptr<unsigned int>>(B + (int64_t)k * a.ldb + c)
                                        : (gptr<unsigned int>)(const void *)kZeroBlock);
                 }
             }
-        } else {
-            const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
+            return;
+        }
 #pragma unroll
-            for (int u = 0; u < B8; ++u) {
-                const int f = tid + u * NT;
-                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
-                const int c0 = min(col0 + cp, N - 1), c1 = min(col0 + cp + 1, N - 1);
+        for (int u = 0; u < A8; ++u) {
+            const int f = tid + u * NT;
+            const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
+            const gptr<unsigned short> row = A + (int64_t)min(row0 + rr, M - 1) * a.lda;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = k0 + kr + e;
-                    const gptr<unsigned short> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
-                    const unsigned int lo = *(row ? row + c0 : zero), hi = *(row ? row + c1 : zero);
-                    rb[u][e] = lo | (hi << 16);
-                }
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + c8 + e;
+                ra[u][e] = *(k < K ? row + k : zero);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B8; ++u) {
+            const int f = tid + u * NT;
+            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
+            const int c0 = min(col0 + cp, N - 1), c1 = min(col0 + cp + 1, N - 1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + kr + e;
+                const gptr<unsigned short> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
+                const unsigned int lo = *(row ? row + c0 : zero), hi = *(row ? row + c1 : zero);
+                rb[u][e] = lo | (hi << 16);
             }
         }
     };
@@ -458,7 +521,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         for (int u = 0; u < A8; ++u) {
             const int f = tid + u * NT;
             const int rr = f / (BK / 8), c8 = (f % (BK / 8)) * 8;
-            *reinterpret_cast<u16x8 *>(&As[st][rr * LD_S + c8]) = ra[u];
+            *reinterpret_cast<u16x8 *>(&As0[st * L::A + rr * LD_S + c8]) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
@@ -471,13 +534,13 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
                 lo[e] = (w0 & 0xffffu) | (w1 << 16);
                 hi[e] = (w0 >> 16) | (w1 & 0xffff0000u);
             }
-            *reinterpret_cast<u32x4 *>(&Bt[st][cp * LD_S + kr]) = lo;
-            *reinterpret_cast<u32x4 *>(&Bt[st][(cp + 1) * LD_S + kr]) = hi;
+            *reinterpret_cast<u32x4 *>(&Bt0[st * L::B + cp * LD_S + kr]) = lo;
+            *reinterpret_cast<u32x4 *>(&Bt0[st * L::B + (cp + 1) * LD_S + kr]) = hi;
         }
     };
     auto compute = [&](int st) {
-        const unsigned short *as = &As[st][(wm * WTM + r) * LD_S + h * (BK / 2)];
-        const unsigned short *bs = &Bt[st][(wn * WTN + r) * LD_S + h * (BK / 2)];
+        const unsigned short *as = &As0[st * L::A + (wm * WTM + r) * LD_S + h * (BK / 2)];
+        const unsigned short *bs = &Bt0[st * L::B + (wn * WTN + r) * LD_S + h * (BK / 2)];
 #pragma unroll
         for (int kc = 0; kc < BK / 2; kc += 8) {
             bf16x8 af[TM], bf[TN];
@@ -493,38 +556,38 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         }
     };
 
-    const int KT = (K + BK - 1) / BK;
-    // leading K steps that need no guards: all of them for an interior tile
-    // on aligned rows, except a partial last one
-    const int KF = (vec && interior) ? K / BK : 0;
+    // the K steps [kt0, kt1) of this workgroup: all of K, or its share of a
+    // product split along K.  Leading steps that need no guards: all of them
+    // for an interior tile on aligned rows, except a partial last one.
+    const int KF = (vec && interior) ? max(kt0, min(K / BK, kt1)) : kt0;
     if (STAGES == 2) {
-        if (KT > 0) {
-            if (KF > 0)
-                gload_fast(0);
+        if (kt1 > kt0) {
+            if (KF > kt0)
+                gload_fast(kt0 * BK);
             else
-                gload(0);
+                gload(kt0 * BK);
             sstore(0);
         }
         __syncthreads();
-        int kt = 0;
+        int kt = kt0;
         // steps whose successor is unguarded too: a loop without branches, so
         // the next step's loads stay in flight while this step multiplies
         for (; kt + 1 < KF; ++kt) {
-            const int cur = kt & 1;
+            const int cur = (kt - kt0) & 1;
             gload_fast((kt + 1) * BK);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
         }
-        for (; kt < KT; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < KT) gload((kt + 1) * BK);
+        for (; kt < kt1; ++kt) {
+            const int cur = (kt - kt0) & 1;
+            if (kt + 1 < kt1) gload((kt + 1) * BK);
             compute(cur);
-            if (kt + 1 < KT) sstore(cur ^ 1);
+            if (kt + 1 < kt1) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
-        int kt = 0;
+        int kt = kt0;
         for (; kt < KF; ++kt) {
             gload_fast(kt * BK);
             __syncthreads();
@@ -532,7 +595,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             __syncthreads();
             compute(0);
         }
-        for (; kt < KT; ++kt) {
+        for (; kt < kt1; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
@@ -551,78 +614,183 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
                 const int gr = row0 + wm * WTM + i * 32 + 8 * (v / 4) + 4 * h + (v % 4);
                 if (interior || (gr < M && gc < N)) {
                     const gmut<float> p = C + (int64_t)gr * a.ldc + gc;
-                    *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
+                    if (a.splits > 1)  // a share of K: added to C, which holds the other shares' sums
+                        unsafeAtomicAdd((float *)p, acc[i][j][v]);
+                    else
+                        *p = a.accumulate ? *p + acc[i][j][v] : acc[i][j][v];
                 }
             }
         }
 }
 
 // ------------------------------------------------------------------ single product
+// Split along K (a.splits = S > 1): the grid holds S x tiles workgroups, share
+// by share; workgroup b takes share b / tiles of tile b % tiles, the K steps
+// [KT s / S, KT (s + 1) / S) of the product's KT = ceil(K / BK).  Programs of
+// 1024 work-items are never split (kSplittableThreads): their registers are
+// at the limit already.
+template <int BK>
+__device__ __forceinline__ void k_share(const MmArgs &a, int64_t tiles, int64_t *b, int *kt0, int *kt1) {
+    const int KT = (a.K + BK - 1) / BK;
+    *kt0 = 0;
+    *kt1 = KT;
+    if (a.splits > 1) {
+        const int s = (int)(*b / tiles);
+        *b -= (int64_t)s * tiles;
+        *kt0 = (int)((int64_t)KT * s / a.splits);
+        *kt1 = (int)((int64_t)KT * (s + 1) / a.splits);
+    }
+}
+
 // WIDE: 16-byte loads along aligned rows; the element-load twin (WIDE =
 // false) is a kernel of its own, so neither carries the other's load path.
 // The twins of workgroups up to 256 work-items load at chosen addresses (all
 // their steps take the edge path).
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
-__device__ __forceinline__ void mfma_f32(const MmArgs &a) {
+__device__ __forceinline__ void mfma_f32(const MmArgs &a0) {
+    MmArgs a = a0;
+    if constexpr (64 * WM * WN > kSplittableThreads) a.splits = 0;
     int tm, tn;
-    tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE);
+    __shared__ __attribute__((aligned(16))) float lds[F32Lds<BM, BN, BK, STAGES>::floats];
+    int64_t b = blockIdx.x;
+    int kt0, kt1;
+    k_share<BK>(a, (int64_t)((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), &b, &kt0, &kt1);
+    tile_of(b, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, lds, kt0, kt1);
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
-__device__ __forceinline__ void mfma_bf16(const MmArgs &a) {
+__device__ __forceinline__ void mfma_bf16(const MmArgs &a0) {
+    MmArgs a = a0;
+    if constexpr (64 * WM * WN > kSplittableThreads) a.splits = 0;
     int tm, tn;
-    tile_of(blockIdx.x, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE);
+    __shared__ __attribute__((aligned(16))) unsigned short lds[Bf16Lds<BM, BN, BK, STAGES>::elems];
+    int64_t b = blockIdx.x;
+    int kt0, kt1;
+    k_share<BK>(a, (int64_t)((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), &b, &kt0, &kt1);
+    tile_of(b, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, lds, kt0, kt1);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
 // Many independent products in one launch; tile t belongs to group
 // tile_group[t] and is tile t - tile_start of that group, numbered row-major
 // over its tiles (a product's tiles are consecutive).  Workgroup b runs on XCD
-// b % 8, so XCD x is given the contiguous tile range [x T / 8, (x + 1) T / 8),
+// b % 8, so XCD x is given the tile range [bin_first[x], bin_first[x + 1]),
 // which its workgroups stride over: a product's tiles then share one XCD's L2
 // (striding over all tiles would spread them over every XCD and fetch the same
-// panels into eight caches).  Grids of fewer than 8 workgroups stride over all
-// tiles.
+// panels into eight caches).  The host orders and cuts the ranges (by
+// estimated cost, most expensive tiles first).  Grids of fewer than 8
+// workgroups stride over all tiles.
 struct GroupWalk {
     int64_t t, end, stride;
-    __device__ __forceinline__ explicit GroupWalk(int64_t total) {
+    __device__ __forceinline__ explicit GroupWalk(const GroupArgs &g) {
         const int64_t G = gridDim.x, b = blockIdx.x;
-        if (G < XCDS) {
+        if (G < kXcds) {
             t = b;
-            end = total;
+            end = g.total_tiles;
             stride = G;
         } else {
-            const int64_t x = b % XCDS;
-            t = total * x / XCDS + b / XCDS;
-            end = total * (x + 1) / XCDS;
-            stride = (G - x + XCDS - 1) / XCDS;  // workgroups on XCD x
+            const int x = (int)(b % kXcds);
+            t = g.bin_first[x] + b / kXcds;
+            end = g.bin_first[x + 1];
+            stride = (G - x + kXcds - 1) / kXcds;  // workgroups on XCD x
         }
     }
 };
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
-    for (GroupWalk w(g.total_tiles); w.t < w.end; w.t += w.stride) {
+    __shared__ __attribute__((aligned(16))) float lds[F32Lds<BM, BN, BK, STAGES>::floats];
+    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
         const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
-        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0);
+        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, lds, 0, (d.K + BK - 1) / BK);
     }
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
-    for (GroupWalk w(g.total_tiles); w.t < w.end; w.t += w.stride) {
+    __shared__ __attribute__((aligned(16))) unsigned short lds[Bf16Lds<BM, BN, BK, STAGES>::elems];
+    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
         const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
-        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0);
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, lds, 0, (d.K + BK - 1) / BK);
+    }
+}
+
+// Mixed grouped kernels: each product's tiles run the program kMixedTile[prog]
+// of its descriptor; one LDS allocation, the largest program's, serves all.
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <int STAGES> struct MixedLds {
+    static constexpr int f32 =
+        cmax(cmax(F32Lds<kMixedTile[0][0], kMixedTile[0][1], kMixedBk[0], STAGES>::floats,
+                  F32Lds<kMixedTile[1][0], kMixedTile[1][1], kMixedBk[0], STAGES>::floats),
+             cmax(F32Lds<kMixedTile[2][0], kMixedTile[2][1], kMixedBk[0], STAGES>::floats,
+                  F32Lds<kMixedTile[3][0], kMixedTile[3][1], kMixedBk[0], STAGES>::floats));
+    static constexpr int bf16 =
+        cmax(cmax(Bf16Lds<kMixedTile[0][0], kMixedTile[0][1], kMixedBk[2], STAGES>::elems,
+                  Bf16Lds<kMixedTile[1][0], kMixedTile[1][1], kMixedBk[2], STAGES>::elems),
+             cmax(Bf16Lds<kMixedTile[2][0], kMixedTile[2][1], kMixedBk[2], STAGES>::elems,
+                  Bf16Lds<kMixedTile[3][0], kMixedTile[3][1], kMixedBk[2], STAGES>::elems));
+};
+
+template <int P, int STAGES>
+__device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int64_t local, int tiles_n, float *lds) {
+    constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
+    const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
+    mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds, 0,
+                                                           (a.K + kMixedBk[0] - 1) / kMixedBk[0]);
+}
+
+template <int P, int STAGES>
+__device__ __forceinline__ void mixed_bf16_tile(const MmArgs &a, int64_t local, int tiles_n, unsigned short *lds) {
+    constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
+    const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
+    mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds, 0,
+                                                            (a.K + kMixedBk[2] - 1) / kMixedBk[2]);
+}
+
+template <int STAGES>
+__device__ __forceinline__ void grouped_mixed_f32(const GroupArgs &g) {
+    static_assert(kMixedPrograms == 4, "one case per program");
+    __shared__ __attribute__((aligned(16))) float lds[MixedLds<STAGES>::f32];
+    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
+        const GroupDesc &d = g.descs[g.tile_group[w.t]];
+        const int64_t local = w.t - d.tile_start;
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
+        __syncthreads();  // the previous tile's LDS reads are done
+        switch (d.prog) {
+        case 0: mixed_f32_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
+        case 1: mixed_f32_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
+        case 2: mixed_f32_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
+        default: mixed_f32_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
+        }
+    }
+}
+
+template <int STAGES>
+__device__ __forceinline__ void grouped_mixed_bf16(const GroupArgs &g) {
+    static_assert(kMixedPrograms == 4, "one case per program");
+    __shared__ __attribute__((aligned(16))) unsigned short lds[MixedLds<STAGES>::bf16];
+    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
+        const GroupDesc &d = g.descs[g.tile_group[w.t]];
+        const int64_t local = w.t - d.tile_start;
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
+        __syncthreads();
+        switch (d.prog) {
+        case 0: mixed_bf16_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
+        case 1: mixed_bf16_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
+        case 2: mixed_bf16_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
+        default: mixed_bf16_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
+        }
     }
 }
 

@@ -148,6 +148,119 @@ __device__ __forceinline__ void valu_tiled(const MmArgs &a) {
     }
 }
 
+// valu_tiled2 (the 2-D micro-tile program, Fig. 4's kernel with outputs per
+// work-item along M as well): a workgroup of BX x BY work-items owns a tile
+// of BY * SY rows and BX * SX columns; work-item (ty, tx) computes the outputs
+// at rows row0 + ty + v * BY (v < SY) and columns col0 + tx + w * BX (w < SX),
+// so a store of the workgroup still writes consecutive columns per row.  The
+// LDS tiles are the A tile (BY * SY) x BK, rows padded by one element, and
+// the B tile BK x (BX * SX), with a K extent BK of its own.  Per k a
+// work-item reads SY + SX LDS words for SY * SX multiply-adds (the paper's
+// program, SY = 1, reads 1 + S for S), which is what lifts the LDS bound.
+// Each output sums k in ascending order, as the one-row program does.
+template <typename T, int BX, int BY, int SX, int SY, int BK>
+__device__ __forceinline__ void valu_tiled2(const MmArgs &a) {
+    using U = typename Acc<T>::type;
+    constexpr int NT = BX * BY;
+    constexpr int TM = BY * SY;
+    constexpr int TN = BX * SX;
+    __shared__ T As[TM][BK + 1];
+    __shared__ T Bs[BK][TN];
+
+    const T *__restrict__ A = static_cast<const T *>(a.A);
+    const T *__restrict__ B = static_cast<const T *>(a.B);
+    T *__restrict__ C = static_cast<T *>(a.C);
+    const int M = a.M, N = a.N, K = a.K;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int tiles_n = (N + TN - 1) / TN;
+    const int64_t tiles = (int64_t)((M + TM - 1) / TM) * tiles_n;
+    constexpr int UA = (TM * BK + NT - 1) / NT, UB = (BK * TN + NT - 1) / NT;
+
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int row0 = (int)(t / tiles_n) * TM;
+        const int col0 = (int)(t % tiles_n) * TN;
+        U acc[SY][SX];
+#pragma unroll
+        for (int v = 0; v < SY; ++v)
+#pragma unroll
+            for (int w = 0; w < SX; ++w) {
+                const int row = row0 + ty + v * BY, col = col0 + tx + w * BX;
+                acc[v][w] = (a.accumulate && row < M && col < N) ? Acc<T>::from(C[(int64_t)row * a.ldc + col]) : U(0);
+            }
+        const bool inside = row0 + TM <= M && col0 + TN <= N;
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            if (inside && k0 + BK <= K) {
+                // the whole K tile in range: unguarded loads, all in flight
+                // before the first LDS store
+                T va[UA], vb[UB];
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const int e = tid + u * NT;
+                    if ((TM * BK) % NT == 0 || e < TM * BK)
+                        va[u] = A[(int64_t)(row0 + e / BK) * a.lda + k0 + e % BK];
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = tid + u * NT;
+                    if ((BK * TN) % NT == 0 || e < BK * TN)
+                        vb[u] = B[(int64_t)(k0 + e / TN) * a.ldb + col0 + e % TN];
+                }
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const int e = tid + u * NT;
+                    if ((TM * BK) % NT == 0 || e < TM * BK) As[e / BK][e % BK] = va[u];
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = tid + u * NT;
+                    if ((BK * TN) % NT == 0 || e < BK * TN) Bs[e / TN][e % TN] = vb[u];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < UA; ++u) {
+                    const int e = tid + u * NT;
+                    if ((TM * BK) % NT == 0 || e < TM * BK) {
+                        const int r = e / BK, c = e % BK;
+                        const int gr = row0 + r, gc = k0 + c;
+                        As[r][c] = (gr < M && gc < K) ? A[(int64_t)gr * a.lda + gc] : T(0);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = tid + u * NT;
+                    if ((BK * TN) % NT == 0 || e < BK * TN) {
+                        const int r = e / TN, c = e % TN;
+                        const int gr = k0 + r, gc = col0 + c;
+                        Bs[r][c] = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : T(0);
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; ++kk) {
+                U av[SY], bv[SX];
+#pragma unroll
+                for (int v = 0; v < SY; ++v) av[v] = (U)As[ty + v * BY][kk];
+#pragma unroll
+                for (int w = 0; w < SX; ++w) bv[w] = (U)Bs[kk][tx + w * BX];
+#pragma unroll
+                for (int v = 0; v < SY; ++v)
+#pragma unroll
+                    for (int w = 0; w < SX; ++w) acc[v][w] = Acc<T>::mad(acc[v][w], av[v], bv[w]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int v = 0; v < SY; ++v)
+#pragma unroll
+            for (int w = 0; w < SX; ++w) {
+                const int row = row0 + ty + v * BY, col = col0 + tx + w * BX;
+                if (row < M && col < N) C[(int64_t)row * a.ldc + col] = Acc<T>::to(acc[v][w]);
+            }
+    }
+}
+
 template <typename T, int BX, int BY, int S>
 __device__ __forceinline__ void valu_direct(const MmArgs &a) {
     using U = typename Acc<T>::type;

@@ -26,6 +26,8 @@ namespace pk {
 // Largest M, N or K accepted: kernels index rows and columns in 32-bit
 // integers, and a tile rounded up past the last row or column must still fit.
 constexpr int64_t kMaxDim = 0x7fff0000;
+// Largest number of shares of K a product is split into.
+constexpr int kMaxSplits = 16;
 
 
 // ------------------------------------------------------------------ errors

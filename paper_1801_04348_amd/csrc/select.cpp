@@ -38,6 +38,7 @@ namespace pk {
 namespace {
 constexpr double kLaunchSeconds = 4e-6;
 constexpr double kHbmBytesPerSecond = 8e12;
+constexpr double kAtomicAddsPerSecond = 2e11;  // float atomic additions to C, whole device
 
 int elem_bytes(int dtype) { return dtype == PK_BF16 ? 2 : 4; }
 
@@ -58,6 +59,12 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     // s = 1, 2, 4, 8 of the 32 multiply-adds per clock.
     const double s = std::max(1, e.s);
     double mads = dtype == PK_I32 ? 32.0 : 64.0;
+    if (e.family == PK_FAMILY_VALU2) {
+        // 2-D micro-tiles: (s + sy) / (s sy) LDS words per multiply-add
+        // against about 24 words per clock, up to the ALU rate
+        const double sy = std::max(1, e.sy);
+        return 2.0 * lanes * std::min(mads * (dtype == PK_I32 ? 0.95 : 1.0), 24.0 * s * sy / (s + sy));
+    }
     if (e.variant & PK_VALU_NOLDS)
         mads = 1.0;
     else if (dtype == PK_I32)
@@ -85,8 +92,18 @@ double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes
     return bytes * (tiles >= ncu ? imbalance : 1.0) / bw + 0.5e-6 * rounds + 3e-6;
 }
 
+std::vector<int> k_splits(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K) {
+    std::vector<int> out;
+    if (e.family != PK_FAMILY_MFMA || e.bk <= 0 || e.threads > pkk::kSplittableThreads) return out;
+    const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
+    const int64_t ksteps = (K + e.bk - 1) / e.bk;
+    const int64_t ncu = std::max<int32_t>(m.cu_count, 1);
+    for (int ks = 2; ks <= kMaxSplits && 2 * ks <= ksteps && tiles * (ks / 2) < 2 * ncu; ks *= 2) out.push_back(ks);
+    return out;
+}
+
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K,
-                        bool wide) {
+                        bool wide, int ks) {
     // Per compute unit: the busiest one holds ceil(tiles / NCU) tiles, `res`
     // of them resident at once; each K step of a round costs the larger of
     // the resident tiles' arithmetic at the unit's rate and one step's
@@ -97,12 +114,14 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const int64_t ncu = std::max<int32_t>(m.cu_count, 1);
     const int wave = m.wave > 0 ? m.wave : 64;
     const int64_t tm = (M + e.tile_m - 1) / e.tile_m, tn = (N + e.tile_n - 1) / e.tile_n;
-    const int64_t tiles = std::max<int64_t>(tm * tn, 1);
+    ks = std::max(ks, 1);
+    // a product split along K runs ks workgroups per tile, each over its share
+    const int64_t tiles = std::max<int64_t>(tm * tn, 1) * ks;
     const int64_t per_cu = (tiles + ncu - 1) / ncu;
     const int64_t res = std::min(blocks_per_cu(m, e), per_cu);
     const int64_t rounds = (per_cu + res - 1) / res;
     const int bk = e.bk > 0 ? e.bk : 1;
-    const double ksteps = (double)((std::max<int64_t>(K, 1) + bk - 1) / bk);
+    const double ksteps = std::ceil((double)((std::max<int64_t>(K, 1) + bk - 1) / bk) / ks);
     const double flops_step = 2.0 * e.tile_m * e.tile_n * bk;
     const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
     const bool mfma = e.family == PK_FAMILY_MFMA;
@@ -125,7 +144,12 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double es = elem_bytes(dtype);
     const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
     const double hbm = (es * ((double)M * K + (double)K * N) + 4.0 * (double)M * N) / kHbmBytesPerSecond;
-    return std::max(compute, std::max(tile_bytes / kHbmBytesPerSecond, hbm)) + kLaunchSeconds;
+    // shares of K: clearing C (a second launch) and one atomic addition per
+    // output and share
+    const double split = ks > 1 ? kLaunchSeconds + 4.0 * (double)M * N / kHbmBytesPerSecond +
+                                      (double)ks * M * N / kAtomicAddsPerSecond
+                                : 0.0;
+    return std::max(compute, std::max(tile_bytes / kHbmBytesPerSecond, hbm)) + split + kLaunchSeconds;
 }
 
 double tile_work_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K) {
@@ -155,12 +179,13 @@ void fill_params(const pk_table *tbl, const Candidate &c, int dtype, pk_params *
     point_params(c.family, part->fam.points[c.point], out);
     out->leaf = c.leaf;
     out->variant = c.variant;
+    out->ks = c.ks > 1 ? c.ks : 0;
 }
 
 std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K, const void *A,
                                 int64_t lda, const void *B, int64_t ldb) {
     std::vector<Candidate> out;
-    for (int family : {PK_FAMILY_VALU, PK_FAMILY_MFMA}) {  // the product families
+    for (int family : {PK_FAMILY_VALU, PK_FAMILY_VALU2, PK_FAMILY_MFMA}) {  // the product families
         const pk_table::Part *part = tbl->part(family, dtype);
         if (!part || !part->supported) continue;
         // MFMA programs read unaligned rows element by element: feasible, slower
@@ -177,6 +202,12 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
             if (!c.entry || (!wide && !element_twin(*c.entry))) continue;
             c.estimate = estimate_seconds(tbl->machine, *c.entry, dtype, M, N, K, wide);
             out.push_back(c);
+            for (int ks : k_splits(tbl->machine, *c.entry, M, N, K)) {  // the same program split along K
+                Candidate d = c;
+                d.ks = ks;
+                d.estimate = estimate_seconds(tbl->machine, *c.entry, dtype, M, N, K, wide, ks);
+                out.push_back(d);
+            }
         }
     }
     return out;
@@ -245,11 +276,13 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
                      [&](size_t x, size_t y) { return cands[x].estimate < cands[y].estimate; });
     for (size_t i : order) {
         const KernelEntry &e = *cands[i].entry;
+        MmArgs ca = args;
+        ca.splits = cands[i].ks > 1 ? cands[i].ks : 0;
         // warm-up launch, itself timed: a candidate whose one launch already
         // takes over a millisecond (launch latency is then negligible) and
         // twice the best mean so far cannot win; its one-launch time is kept
         float wms = 0.f;
-        if (hipEventRecord(e0, s) != hipSuccess || launch(tbl->machine, e, args, s) != PK_OK ||
+        if (hipEventRecord(e0, s) != hipSuccess || launch(tbl->machine, e, ca, s) != PK_OK ||
             hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&wms, e0, e1) != hipSuccess) {
             (void)hipGetLastError();
@@ -270,7 +303,7 @@ int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_
         bool ok = hipEventRecord(e0, s) == hipSuccess;
         int reps = 0;
         while (ok) {
-            ok = launch(tbl->machine, e, args, s) == PK_OK;
+            ok = launch(tbl->machine, e, ca, s) == PK_OK;
             ++reps;
             if (ok && (reps == 3 || reps % 8 == 0)) {
                 ok = hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
@@ -320,7 +353,7 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         std::vector<float> X(cands.size() * PK_NFEATURES), pred(cands.size());
         const bool wide = !A || wide_rows(dtype, A, lda, B, ldb);
         for (size_t i = 0; i < cands.size(); ++i)
-            features(tbl->machine, *cands[i].entry, M, N, K, wide, &X[i * PK_NFEATURES]);
+            features(tbl->machine, *cands[i].entry, M, N, K, wide, cands[i].ks, &X[i * PK_NFEATURES]);
         costmodel_predict(*model, tbl->device, X.data(), (int64_t)cands.size(), pred.data());
         std::vector<int> order(cands.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;

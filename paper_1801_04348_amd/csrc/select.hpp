@@ -15,6 +15,7 @@ struct Candidate {
     int leaf = -1;
     int variant = 0;
     const KernelEntry *entry = nullptr;
+    int ks = 1;             // MFMA programs: shares of K (a launch parameter)
     double estimate = 0.0;  // analytic time estimate, seconds
 };
 
@@ -27,7 +28,12 @@ std::vector<Candidate> feasible(const pk_table *tbl, int dtype, int64_t M, int64
 // Analytic time of one launch (the CASE score).
 // `wide`: the operands' rows are aligned for the MFMA programs' 16-byte loads.
 double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K,
-                        bool wide = true);
+                        bool wide = true, int ks = 1);
+
+// Shares of K worth trying for an MFMA program at (M, N, K): 2, 4, ... while
+// the product has fewer tiles than two per compute unit at the previous
+// share count and every share keeps at least two K steps.
+std::vector<int> k_splits(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K);
 
 // Compute-unit seconds of a product's tiles under a program when every
 // compute unit is kept full of its workgroups (the work a persistent grouped
@@ -64,6 +70,9 @@ struct Operands {
 int time_candidates(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t K,
                     const std::vector<Candidate> &cands, std::vector<double> *secs, const Operands *ops, int *best);
 
+// Queues C[i][j] = 0 (i < M, j < N, rows of ldc floats) on `stream` (fill.hip).
+int zero_matrix(const pk_machine &m, void *C, int64_t ldc, int64_t M, int64_t N, hipStream_t stream);
+
 // helpers shared with capi.cpp
 int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e);
 int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N);
@@ -77,7 +86,8 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
 
 // cost model (costmodel.hip)
 std::string machine_fingerprint(const pk_machine &m);
-void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, float *f);
+void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, int ks,
+              float *f);
 void costmodel_predict(const pk_costmodel &cm, int device, const float *X, int64_t n, float *out);
 
 }  // namespace pk

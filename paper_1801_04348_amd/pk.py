@@ -36,6 +36,7 @@ PK_ERR_PARSE = -8
 PK_F32, PK_I32, PK_BF16 = 0, 1, 2
 PK_FAMILY_VALU, PK_FAMILY_MFMA, PK_FAMILY_TRANSPOSE, PK_FAMILY_MADD, PK_FAMILY_JACOBI, PK_FAMILY_POLYDIV = (
     0, 1, 2, 3, 4, 5)
+PK_FAMILY_VALU2 = 6
 PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_POLYDIV_FUSED, PK_POLYDIV_WIDE = 4, 8
 PK_JACOBI_FUSED = 4
@@ -66,7 +67,7 @@ class pk_machine(ctypes.Structure):
 
 class pk_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("family", "leaf", "variant", "bx", "by", "s", "bk", "bm", "bn", "wm", "wn")]
+                ("family", "leaf", "variant", "bx", "by", "s", "bk", "bm", "bn", "wm", "wn", "ks", "sy")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -75,8 +76,8 @@ class pk_params(ctypes.Structure):
         return "pk_params(%s)" % ", ".join("%s=%d" % kv for kv in self.as_dict().items())
 
 
-def params(family=PK_FAMILY_VALU, leaf=-1, variant=-1, bx=0, by=0, s=0, bk=0, bm=0, bn=0, wm=0, wn=0):
-    return pk_params(family, leaf, variant, bx, by, s, bk, bm, bn, wm, wn)
+def params(family=PK_FAMILY_VALU, leaf=-1, variant=-1, bx=0, by=0, s=0, bk=0, bm=0, bn=0, wm=0, wn=0, ks=0, sy=0):
+    return pk_params(family, leaf, variant, bx, by, s, bk, bm, bn, wm, wn, ks, sy)
 
 
 def machine(**kw) -> pk_machine:
@@ -461,7 +462,7 @@ def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=No
 
 
 # ---------------------------------------------------------------------- cost model
-PK_NFEATURES = 11
+PK_NFEATURES = 12
 
 
 def _fbuf(a):
@@ -653,11 +654,12 @@ def _grouped_sigs(L):
     L.pk_grouped_plan_replay.argtypes = [vp, vp]
     L.pk_grouped_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(pk_params), ctypes.c_int32]
+    L.pk_grouped_plan_kernel.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p)]
     L.pk_grouped_plan_destroy.argtypes = [vp]
     L.pk_grouped_plan_destroy.restype = None
     L.pk_matmul_batched.argtypes = [vp, i32, ctypes.c_int32] + arrs + [ctypes.POINTER(pk_params), vp]
     for n in ("pk_grouped_plan_create", "pk_grouped_plan_run", "pk_grouped_plan_capture", "pk_grouped_plan_replay",
-              "pk_grouped_plan_info", "pk_matmul_batched"):
+              "pk_grouped_plan_info", "pk_grouped_plan_kernel", "pk_matmul_batched"):
         getattr(L, n).restype = i32
     L._grouped_sigs = True
 
@@ -688,6 +690,16 @@ class GroupedPlan:
         _check(lib().pk_grouped_plan_info(self.handle, ctypes.byref(n), ctypes.byref(t), chosen, self.G))
         return n.value, t.value, [chosen[i] for i in range(self.G)]
 
+    def kernels(self):
+        """Names of the plan's launches' kernels, in launch order."""
+        n = self.info()[0]
+        out = []
+        for i in range(n):
+            name = ctypes.c_char_p()
+            _check(lib().pk_grouped_plan_kernel(self.handle, i, ctypes.byref(name)))
+            out.append(name.value.decode())
+        return out
+
 
 def pk_grouped_plan_create(tbl: Table, dtype, As, Bs, Cs, params=None, policy: int = PK_POLICY_CASE,
                            accumulate: bool = False) -> GroupedPlan:
@@ -709,3 +721,4 @@ def pk_matmul_batched(tbl: Table, dtype, As, Bs, Cs, params=None, stream=None):
     G, arrs = _grouped_arrays(As, Bs, Cs, dtype)
     ps = (pk_params * G)(*params) if params is not None else None
     _check(L.pk_matmul_batched(tbl.handle, _dt(dtype), G, *arrs, ps, _stream(stream)))
+

@@ -135,8 +135,9 @@ def test_exhaustive_plan_picks_a_fitting_program(table, dtype):
     n_launch, tiles, chosen = plan.info()
     assert n_launch == 1
     names = {pk.pk_kernel_name(table, c, dtype) for c in chosen}
-    assert len(names) == 1, names
-    say("%s exhaustive grouped pick: %s" % (dtype, names.pop()))
+    say("%s exhaustive grouped pick: %s running %s" % (dtype, plan.kernels(), sorted(names)))
+    if len(names) > 1:
+        assert plan.kernels()[0].startswith("pk_grouped_mixed_%s" % dtype)
     for c in Cs:
         c.fill_(float("nan"))              # the selection runs wrote C; start again
     plan.run()
@@ -184,3 +185,109 @@ def test_4096_products_sampled(table, dtype):
         a = Ah[offA[g]:offA[g + 1]].view(M, int(lda[g]))[:, :K].contiguous()
         b = Bh[offB[g]:offB[g + 1]].view(K, int(ldb[g]))[:, :N].contiguous()
         assert rel_fro(Cs[g].cpu().numpy(), om.matmul(a, b, dtype)) <= tol, g
+
+
+MIXED = [(64, 64), (128, 64), (64, 128), (128, 128)]
+MIXED_BK = {"f32": 32, "bf16": 64}
+
+
+def mixed_params(dtype, G, stage, programs=MIXED):
+    return [pk.params(family=pk.PK_FAMILY_MFMA, bm=programs[g % len(programs)][0], bn=programs[g % len(programs)][1],
+                      bk=MIXED_BK[dtype], wm=2, wn=2, variant=stage) for g in range(G)]
+
+
+@pytest.mark.parametrize("dtype,stage", [("f32", 0), ("f32", pk.PK_MFMA_SINGLE), ("bf16", pk.PK_MFMA_SINGLE)])
+def test_mixed_tiles_one_launch_bit_identical(table, dtype, stage):
+    # every product its own tile program, all four of the mixed kernel's
+    # programs in one plan: one launch, each product equal bit for bit to the
+    # single-product launch of its program, and to the oracle
+    dims, host, dev = make_groups(48, seed=17, dtype=dtype, aligned_every=2, hi=300)
+    As, Bs, Cs = zip(*dev)
+    ps = mixed_params(dtype, len(As), stage)
+    plan = pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs, params=ps)
+    n_launch, tiles, chosen = plan.info()
+    kernels = plan.kernels()
+    say("%s stage %d mixed plan: %s, %d tiles" % (dtype, stage, kernels, tiles))
+    assert n_launch == 1 and kernels[0].startswith("pk_grouped_mixed_%s" % dtype), kernels
+    assert len({(c.bm, c.bn) for c in chosen}) == 4
+    plan.run()
+    torch.cuda.synchronize()
+    tol = 1e-5 if dtype == "f32" else 1e-2
+    for g, ((a, b), (ad, bd, cd)) in enumerate(zip(host, dev)):
+        got = cd.cpu()
+        assert not torch.isnan(got).any(), g
+        assert rel_fro(got.numpy(), om.matmul(a, b, dtype)) <= tol, (g, dims[g])
+        C1 = torch.empty_like(cd)
+        pk.pk_matmul(table, chosen[g], dtype, ad, bd, C1)
+        torch.cuda.synchronize()
+        assert torch.equal(C1.cpu(), got), (g, dims[g], chosen[g])
+
+
+def test_mixed_tiles_accumulate_visits_each_tile_once(table):
+    dims, host, dev = make_groups(40, seed=19, dtype="f32", aligned_every=3, hi=280)
+    As, Bs, Cs = zip(*dev)
+    ps = mixed_params("f32", len(As), 0)
+    pk.pk_matmul_batched(table, "f32", As, Bs, Cs, params=ps)
+    torch.cuda.synchronize()
+    first = [c.cpu().clone() for c in Cs]
+    for c in Cs:
+        c.zero_()
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, params=ps, accumulate=True)
+    assert plan.info()[0] == 1
+    plan.run()
+    plan.run()
+    torch.cuda.synchronize()
+    for g, c in enumerate(Cs):
+        assert not torch.isnan(first[g]).any()
+        assert torch.allclose(c.cpu(), 2 * first[g], rtol=1e-6, atol=1e-6), g
+
+
+def test_two_stage_counts_get_launches_of_their_own(table):
+    # one mixed kernel runs one stage count: products given two programs of
+    # different stage counts run as one launch per grouped instance
+    dims, host, dev = make_groups(24, seed=23, dtype="f32", aligned_every=1, hi=300)
+    As, Bs, Cs = zip(*dev)
+    ps = mixed_params("f32", len(As), 0, programs=[(64, 64)])
+    for g in range(0, len(ps), 3):
+        ps[g] = pk.params(family=pk.PK_FAMILY_MFMA, bm=128, bn=128, bk=32, wm=2, wn=2, variant=pk.PK_MFMA_SINGLE)
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, params=ps)
+    kernels = plan.kernels()
+    say("launches: %s" % kernels)
+    assert sorted(kernels) == ["pk_grouped_f32_128x128x32_w2x2_st1", "pk_grouped_f32_64x64x32_w2x2_st2"]
+    plan.run()
+    torch.cuda.synchronize()
+    for (a, b), (ad, bd, cd) in zip(host, dev):
+        assert rel_fro(cd.cpu().numpy(), om.matmul(a, b, "f32")) <= 1e-5
+
+
+def test_case_plan_is_one_launch_and_learned_is_refused(table):
+    dims, host, dev = make_groups(64, seed=29, dtype="f32", aligned_every=2, lo=16, hi=512)
+    As, Bs, Cs = zip(*dev)
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs)
+    assert plan.info()[0] == 1, plan.kernels()
+    with pytest.raises(pk.PkError) as e:
+        pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, policy=pk.PK_POLICY_LEARNED)
+    assert e.value.code == pk.PK_ERR_INVALID_ARG
+
+
+def test_empty_and_k0_products_in_a_mixed_plan(table):
+    shapes = [(0, 5, 7), (6, 0, 3), (40, 70, 0), (33, 65, 17), (1, 1, 1), (129, 130, 131)]
+    As, Bs, Cs, refs = [], [], [], []
+    for i, (M, N, K) in enumerate(shapes):
+        a = inputs.uniform_f32((M, K), seed=300 + 2 * i)
+        b = inputs.uniform_f32((K, N), seed=301 + 2 * i)
+        As.append(a.cuda())
+        Bs.append(b.cuda())
+        Cs.append(torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda"))
+        refs.append(om.matmul(a, b, "f32") if M * N > 0 else None)
+    ps = mixed_params("f32", len(shapes), 0)
+    pk.pk_matmul_batched(table, "f32", As, Bs, Cs, params=ps)
+    torch.cuda.synchronize()
+    for i, (M, N, K) in enumerate(shapes):
+        if M * N == 0:
+            continue
+        got = Cs[i].cpu().numpy()
+        if K == 0:
+            assert np.all(got == 0.0)
+        else:
+            assert rel_fro(got, refs[i]) <= 1e-5, shapes[i]

@@ -103,8 +103,11 @@ def test_measure_and_exhaustive_pick(table, dtype, shape):
     say("pk_measure %s %s" % (dtype, shape))
     res = pk.pk_measure(table, dtype, M, N, K, Ad, Bd, C)
     # every feasible (leaf, E) is timed: aligned operands, so every point
-    # with a leaf is a candidate
-    assert len(res) == feasible_count(table, dtype), (len(res), feasible_count(table, dtype))
+    # with a leaf is a candidate, run whole and (MFMA programs, few tiles)
+    # split along K
+    whole = [p for p, _ in res if p.ks <= 1]
+    assert len(whole) == feasible_count(table, dtype), (len(whole), feasible_count(table, dtype))
+    assert all(p.family == pk.PK_FAMILY_MFMA for p, _ in res if p.ks > 1)
     secs = np.array([s for _, s in res])
     assert np.all(np.isfinite(secs)) and np.all(secs > 0), secs
     # distinct (leaf, E) pairs; two of them may run one compiled program (a

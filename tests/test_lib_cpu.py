@@ -121,6 +121,8 @@ def test_lds_counter_equals_compiled_lds(gfx_desc):
         assert e["lds_bytes"] == e["lds_compiled"], e["name"]
         if e["family"] == en.VALU:
             assert e["lds_bytes"] == en.valu_lds(e["variant"], e["bx"], e["by"], e["s"])
+        elif e["family"] == en.VALU2:
+            assert e["lds_bytes"] == en.valu2_lds(e["variant"], e["bx"], e["by"], e["s"], e["sy"], e["bk"])
         elif e["family"] == en.TRANSPOSE:
             assert e["lds_bytes"] == en.transpose_lds(e["variant"], e["bx"], e["by"], e["s"])
         elif e["family"] == en.MADD:
@@ -204,7 +206,8 @@ def test_optimality_definition_3_iv(gfx_desc):
              2: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
              3: {"r_V": {"gran"}, "r_T": set()},
              4: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
-             5: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()}}
+             5: {"r_Z": {"gran", "nolds"}, "r_V": {"gran", "nolds"}, "r_T": set()},
+             6: {"r_Z": {"gran"}, "r_V": {"gran"}, "r_T": set()}}
     for part in gfx_desc["parts"]:
         for counter, strategies in sigma[part["family"]].items():
             assert any(strategies <= set(l["applied"]) for l in part["solution"]["leaves"]), (part["family"], counter)
@@ -381,25 +384,38 @@ def test_case_pick_minimises_the_estimate():
     # pk_estimate; the feasible set rebuilt from the bound table
     t = pk.pk_case_table_build(0, machines.gfx950())
     d = pk.pk_case_table_describe(t)
+    ncu = d["machine"]["cu_count"]
     for dtype, dt in (("f32", 0), ("i32", 1), ("bf16", 2)):
-        cands = []
-        for part in d["parts"]:
-            if part["dtype"] != dt or part["family"] not in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_MFMA):
-                continue
-            for i, pt in enumerate(part["points"]):
-                if part["first_leaf"][i] < 0:
+        for M, N, K in ((512, 512, 512), (3000, 8192, 1000), (100, 2000, 64), (512, 512, 8192)):
+            cands = []
+            for part in d["parts"]:
+                fam = part["family"]
+                if part["dtype"] != dt or fam not in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_VALU2, pk.PK_FAMILY_MFMA):
                     continue
-                if part["family"] == pk.PK_FAMILY_VALU:
-                    p = pk.params(family=0, bx=pt[0], by=pt[1], s=pt[2])
-                else:
-                    p = pk.params(family=1, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4])
-                cands.append(p)
-        for M, N, K in ((512, 512, 512), (3000, 8192, 1000), (100, 2000, 64)):
+                for i, pt in enumerate(part["points"]):
+                    if part["first_leaf"][i] < 0:
+                        continue
+                    if fam == pk.PK_FAMILY_VALU:
+                        cands.append(pk.params(family=fam, bx=pt[0], by=pt[1], s=pt[2]))
+                    elif fam == pk.PK_FAMILY_VALU2:
+                        cands.append(pk.params(family=fam, bx=pt[0], by=pt[1], s=pt[2], sy=pt[3], bk=pt[4]))
+                    else:
+                        cands.append(pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4]))
+                        # the shares of K offered: fewer tiles than two per
+                        # compute unit at the previous count, two K steps a share
+                        tiles = -(-M // pt[0]) * -(-N // pt[1])
+                        ks = 2
+                        while (ks <= 16 and 2 * ks <= -(-K // pt[2]) and tiles * (ks // 2) < 2 * ncu
+                               and 64 * pt[3] * pt[4] <= 512):
+                            cands.append(pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4],
+                                                   ks=ks))
+                            ks *= 2
             est = [pk.pk_estimate(t, p, dtype, M, N, K) for p in cands]
             assert all(e > 0 for e in est)
-            want = pk.pk_kernel_name(t, cands[min(range(len(est)), key=est.__getitem__)], dtype)
-            got = pk.pk_kernel_name(t, pk.pk_select(t, dtype, M, N, K, pk.PK_POLICY_CASE), dtype)
-            assert got == want, (dtype, M, N, K)
+            best = cands[min(range(len(est)), key=est.__getitem__)]
+            pick = pk.pk_select(t, dtype, M, N, K, pk.PK_POLICY_CASE)
+            assert (pk.pk_kernel_name(t, pick, dtype), pick.ks) == (pk.pk_kernel_name(t, best, dtype), best.ks), \
+                (dtype, M, N, K)
     with pytest.raises(pk.PkError):
         pk.pk_estimate(t, pk.params(family=pk.PK_FAMILY_TRANSPOSE, bx=32, by=8, s=1), "f32", 1, 1, 1)
 

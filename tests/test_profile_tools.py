@@ -76,3 +76,44 @@ def test_traffic_scaled_by_the_copy(tmp_path):
     res = json.load(open(out))
     assert res["FETCH_SIZE"]["launches"] == 2 and res["FETCH_SIZE"]["factor"] == 2.0
     assert res["bytes_per_launch"] == 100.0 * 1024 * 2 + 40.0 * 1024
+
+
+def test_traffic_every_kernel(tmp_path):
+    copy_kib = (256 << 20) / 1024
+    for counter, cdir in (("FETCH_SIZE", "f"), ("WRITE_SIZE", "w")):
+        d = tmp_path / cdir
+        d.mkdir()
+        names = [COPY] * 3 + ["pk_a"] + [COPY] + ["pk_a", "pk_b", "pk_b"] + [COPY] + ["pk_a"]
+        with open(d / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for i, n in enumerate(names):
+                v = copy_kib if n == COPY else {"pk_a": 10.0, "pk_b": 30.0}[n] * (1 if 5 <= i <= 7 else 50)
+                w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": n, "Counter_Name": counter, "Counter_Value": v})
+    outd = tmp_path / "o"
+    subprocess.run([sys.executable, os.path.join(ROOT, "paper_1801_04348_amd", "traffic.py"), "--fetch",
+                    str(tmp_path / "f"), "--write", str(tmp_path / "w"), "--out-dir", str(outd)],
+                   capture_output=True, text=True, check=True)
+    a = json.load(open(outd / "traffic_pk_a.json"))
+    b = json.load(open(outd / "traffic_pk_b.json"))
+    assert a["bytes_per_launch"] == 2 * 10.0 * 1024 and a["WRITE_SIZE"]["launches"] == 1
+    assert b["bytes_per_launch"] == 2 * 30.0 * 1024 and b["FETCH_SIZE"]["launches"] == 2
+
+
+def test_counter_means_and_ratios(tmp_path):
+    from paper_1801_04348_amd import counters
+    names = [COPY] * 3 + ["pk_a"] + [COPY] + ["pk_a", "pk_a"] + [COPY]
+    with open(tmp_path / "y_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, n in enumerate(names):
+            # two hardware instances per counter and dispatch: summed
+            for inst in range(2):
+                for c, v in (("SQ_VALU_MFMA_BUSY_CYCLES", 30.0 + i), ("GRBM_GUI_ACTIVE", 50.0),
+                             ("SQ_LDS_BANK_CONFLICT", 5.0), ("SQ_LDS_IDX_ACTIVE", 20.0)):
+                    w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": n, "Counter_Name": c, "Counter_Value": v})
+    res = counters.summarize([str(tmp_path)])
+    assert list(res) == ["pk_a"] and res["pk_a"]["dispatches"] == 2
+    m = res["pk_a"]["mean"]
+    assert m["SQ_VALU_MFMA_BUSY_CYCLES"] == 2 * (35.0 + 36.0) / 2 and m["GRBM_GUI_ACTIVE"] == 100.0
+    assert res["pk_a"]["ratios"] == {"mfma_busy_per_active": 0.71, "lds_conflict_per_active": 0.25}
