@@ -19,8 +19,9 @@ Prints one JSON line (rank 0, the only rank):
   exhaustive    when a tuning store for this device exists, the per-shape best
              branch timed in the same run (untimed for `value`; in-sample)
   heldout    the cost model on 40 held-out shapes, every candidate timed live
-  grouped    4096 uneven products in one persistent launch per configuration
-             (graph replay) against a loop of single launches
+  grouped    4096 uneven products in one persistent launch (a tile program
+             per product), CASE and EXHAUSTIVE plans (graph replay), against
+             a loop of single launches
   bf16_dense bfloat16 products at 4096^3 and 8192^3 (CASE, LEARNED and best
              program) against the 2.5 PFLOP/s bf16 matrix peak
   side       the paper's other examples (paper_1801_04348_amd/sidebench.py):
@@ -183,31 +184,16 @@ def bf16_section(tbl, pk, torch, inputs):
     return out
 
 
-def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
+def grouped_section(tbl, pk, torch, inputs, dtype, reps=5):
     """4096 independent products, M, N, K each round(exp(U(ln 16, ln 512)))
     from seed 0, operands packed in three buffers with rows padded to 8
-    elements: one grouped plan replayed from its captured graph, against a
-    loop of 4096 single-product launches (eager, and captured in a graph)."""
+    elements (workloads.grouped_operands): one grouped plan (CASE, and the
+    EXHAUSTIVE auto-tuner's) replayed from its captured graph, against a loop
+    of 4096 single-product launches (eager, and captured in a graph)."""
     import numpy as np
+    from paper_1801_04348_amd import workloads
     G = 4096
-    dims = inputs.group_dims(G, seed=0)
-    lda = (dims[:, 2] + 7) // 8 * 8
-    ldb = (dims[:, 1] + 7) // 8 * 8
-    offA = np.concatenate([[0], np.cumsum(dims[:, 0] * lda)])
-    offB = np.concatenate([[0], np.cumsum(dims[:, 2] * ldb)])
-    offC = np.concatenate([[0], np.cumsum(dims[:, 0] * dims[:, 1])])
-    Ah = inputs.uniform_f32((int(offA[-1]),), seed=11)
-    Bh = inputs.uniform_f32((int(offB[-1]),), seed=12)
-    if dtype == "bf16":
-        Ah, Bh = inputs.bf16_bits(Ah), inputs.bf16_bits(Bh)
-    Ad, Bd = Ah.cuda(), Bh.cuda()
-    Cd = torch.empty((int(offC[-1]),), dtype=torch.float32, device="cuda")
-    As, Bs, Cs = [], [], []
-    for g, (M, N, K) in enumerate(dims):
-        M, N, K = int(M), int(N), int(K)
-        As.append(Ad[offA[g]:offA[g + 1]].view(M, int(lda[g]))[:, :K])
-        Bs.append(Bd[offB[g]:offB[g + 1]].view(K, int(ldb[g]))[:, :N])
-        Cs.append(Cd[offC[g]:offC[g + 1]].view(M, N))
+    dims, As, Bs, Cs = workloads.grouped_operands(torch, inputs, dtype, G=G)
     flops = float(2 * np.prod(dims.astype(np.float64), axis=1).sum())
     es = 2 if dtype == "bf16" else 4
     peak = 2.5e15 if dtype == "bf16" else 157.3e12
@@ -226,7 +212,7 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
-    plan = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=policy)
+    plan = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=pk.PK_POLICY_CASE)
     n_launch, tiles, chosen = plan.info()
     plan.capture()
     t_graph = timed(lambda: plan.replay())
@@ -234,6 +220,7 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
     # the program chosen by timing each candidate plan on these operands
     plan_x = pk.pk_grouped_plan_create(tbl, dtype, As, Bs, Cs, policy=pk.PK_POLICY_EXHAUSTIVE)
     chosen_x = plan_x.info()[2]
+    tiles_of = lambda ch: sorted({"%dx%d" % (c.bm, c.bn) for c in ch})  # noqa: E731
     plan_x.capture()
     t_graph_x = timed(lambda: plan_x.replay())
     picks = [pk.pk_select(tbl, dtype, int(M), int(N), int(K), pk.PK_POLICY_CASE) for (M, N, K) in dims]
@@ -253,9 +240,10 @@ def grouped_section(tbl, pk, torch, inputs, dtype, policy, reps=5):
         loop()
     t_loop_graph = timed(lambda: graph.replay())
     return {"products": G, "gflop": round(flops / 1e9, 2), "launches": n_launch, "tiles": tiles,
-            "program": pk.pk_kernel_name(tbl, chosen[0], dtype),
+            "kernels": plan.kernels(), "tile_programs": tiles_of(chosen),
             "grouped_graph_gflops": round(flops / t_graph / 1e9, 1),
-            "exhaustive_program": pk.pk_kernel_name(tbl, chosen_x[0], dtype),
+            "exhaustive_kernels": plan_x.kernels(), "exhaustive_tile_programs": tiles_of(chosen_x),
+            "exhaustive_launches": plan_x.info()[0],
             "exhaustive_graph_gflops": round(flops / t_graph_x / 1e9, 1),
             "exhaustive_pct_summed_roofline": round(roof / t_graph_x, 4),
             "grouped_gflops": round(flops / t_plan / 1e9, 1),
@@ -510,7 +498,7 @@ def main():
     grouped = None
     bf16 = None
     if not args.sweep_only:
-        grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt, policy) for dt in ("f32", "bf16")}
+        grouped = {dt: grouped_section(tbl, pk, torch, inputs, dt) for dt in ("f32", "bf16")}
         bf16 = bf16_section(tbl, pk, torch, inputs)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,

@@ -72,6 +72,7 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
                                             std::to_string(pkk::kSplittableThreads) + " work-items");
     *pout = *pin;
     point_params(pin->family, pt, pout);
+    pout->ks = pin->ks > 1 ? pin->ks : 0;
     pout->leaf = leaf;
     pout->variant = variant;
     *entry = e;

@@ -371,7 +371,7 @@ bool params_point(int family, const pk_params &p, std::vector<int64_t> *pt) {
 
 void point_params(int family, const std::vector<int64_t> &pt, pk_params *p) {
     p->family = family;
-    p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = p->sy = 0;
+    p->bx = p->by = p->s = p->bk = p->bm = p->bn = p->wm = p->wn = p->sy = p->ks = 0;
     if (family == PK_FAMILY_VALU2) {
         p->bx = (int32_t)pt[0];
         p->by = (int32_t)pt[1];

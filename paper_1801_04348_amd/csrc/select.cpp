@@ -38,7 +38,7 @@ namespace pk {
 namespace {
 constexpr double kLaunchSeconds = 4e-6;
 constexpr double kHbmBytesPerSecond = 8e12;
-constexpr double kAtomicAddsPerSecond = 2e11;  // float atomic additions to C, whole device
+constexpr double kAtomicAddsPerSecond = 4e11;  // float atomic additions to C, whole device
 
 int elem_bytes(int dtype) { return dtype == PK_BF16 ? 2 : 4; }
 
@@ -126,7 +126,7 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
     const bool mfma = e.family == PK_FAMILY_MFMA;
     const bool vi32 = !mfma && dtype == PK_I32;  // int32 VALU: its own fitted knee and barrier cost
-    const double occupancy = std::min(1.0, std::pow(waves_per_simd / (vi32 ? 6.0 : 3.0), 0.25));
+    const double occupancy = std::min(1.0, std::pow(waves_per_simd / (vi32 ? 6.0 : 3.0), mfma ? 0.4 : 0.25));
     // MFMA: the tile's LDS words per output; VALU: workgroups of fewer than
     // 256 work-items lose in proportion
     const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n))
@@ -142,7 +142,8 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double compute =
         narrow * (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
     const double es = elem_bytes(dtype);
-    const double tile_bytes = es * (double)tiles * (double)K * (e.tile_m + e.tile_n);
+    // each workgroup reads its A and B panels over its share of K
+    const double tile_bytes = es * (double)tiles * std::ceil((double)K / ks) * (e.tile_m + e.tile_n);
     const double hbm = (es * ((double)M * K + (double)K * N) + 4.0 * (double)M * N) / kHbmBytesPerSecond;
     // shares of K: clearing C (a second launch) and one atomic addition per
     // output and share

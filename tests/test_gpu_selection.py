@@ -84,7 +84,8 @@ def feasible_count(table, dtype):
     d = pk.pk_case_table_describe(table)
     n = 0
     for part in d["parts"]:
-        if part["family"] in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_MFMA) and part["dtype"] == pk.DTYPES[dtype]:
+        if part["family"] in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_VALU2, pk.PK_FAMILY_MFMA) and \
+                part["dtype"] == pk.DTYPES[dtype]:
             n += sum(1 for leaf in part["first_leaf"] if leaf >= 0)
     return n
 
@@ -226,15 +227,20 @@ def test_costmodel_inference_matches_oracle_network(learned_table, dtype):
     rows = []
     for (M, N, K) in inputs.log_uniform_shapes(40, seed=7):
         for part in d["parts"]:
-            if part["family"] not in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_MFMA) or part["dtype"] != pk.DTYPES[dtype]:
+            fam = part["family"]
+            if fam not in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_VALU2, pk.PK_FAMILY_MFMA) or \
+                    part["dtype"] != pk.DTYPES[dtype]:
                 continue
             for pt, leaf in zip(part["points"], part["first_leaf"]):
                 if leaf < 0:
                     continue
-                if part["family"] == pk.PK_FAMILY_VALU:
+                if fam == pk.PK_FAMILY_VALU:
                     p = pk.params(bx=pt[0], by=pt[1], s=pt[2])
-                else:
-                    p = pk.params(family=pk.PK_FAMILY_MFMA, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4])
+                elif fam == pk.PK_FAMILY_VALU2:
+                    p = pk.params(family=fam, bx=pt[0], by=pt[1], s=pt[2], sy=pt[3], bk=pt[4])
+                else:   # split along K in some rows (where the program allows it)
+                    ks = int(rng.choice([0, 2, 4])) if 64 * pt[3] * pt[4] <= 512 else 0
+                    p = pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4], ks=ks)
                 rows.append(pk.pk_features(learned_table, p, dtype, int(M), int(N), int(K),
                                            wide=bool(rng.integers(0, 2))))
     X = np.array(rows, dtype=np.float32)
