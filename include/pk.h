@@ -354,6 +354,26 @@ int pk_matmul_batched(const pk_table *tbl, pk_dtype dtype, int32_t G, const int6
                       const int64_t *ldb, void *const *C, const int64_t *ldc, const pk_params *per_group_or_null,
                       void *hip_stream);
 
+/* pk_matmul_batched for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same products, the same CASE choice (or the given per-product parameters),
+ * the same kernels, but the launch's descriptors and tile map go to a
+ * workspace that every GPU running the library holds from the table's
+ * creation until the process ends, 4 MiB per device (reached through a static
+ * host staging copy of the same size), instead of device memory allocated for
+ * a plan.  No hipMalloc, hipFree, pinned-memory allocation or allocating
+ * library routine is called.  A layout larger than the workspace (about
+ * 50000 small products) is refused with PK_ERR_INVALID_ARG before any work
+ * is queued.  Every call shares its GPU's workspace: calls in one process are
+ * serialised by a lock and each returns after its work on hip_stream is done
+ * (it synchronizes the stream), so one call's layout is never overwritten by
+ * another's; calls that overlapped on one GPU would race on it.  Errors as
+ * pk_matmul_batched. */
+int pk_matmul_batched_noalloc(const pk_table *tbl, pk_dtype dtype, int32_t G, const int64_t *M, const int64_t *N,
+                              const int64_t *K, const void *const *A, const int64_t *lda, const void *const *B,
+                              const int64_t *ldb, void *const *C, const int64_t *ldc,
+                              const pk_params *per_group_or_null, void *hip_stream);
+
 /* ------------------------------------------------------------------ transposition */
 /* C (N x M) = A (M x N) transposed, 4-byte elements copied bit for bit
  * (dtype PK_F32 or PK_I32), row-major with leading dimensions lda >= N,

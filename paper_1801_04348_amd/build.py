@@ -39,7 +39,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE,
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Rpass-analysis=kernel-resource-usage"]
 HOST_SOURCES = ["engine.cpp", "families.cpp", "capi.cpp", "select.cpp", "registry.cpp", "grouped.cpp", "transpose.cpp",
                 "madd.cpp", "jacobi.cpp"]
-DEVICE_SOURCES = ["costmodel.hip", "polydiv.hip", "probes.hip", "fill.hip"]
+DEVICE_SOURCES = ["costmodel.hip", "polydiv.hip", "probes.hip", "fill.hip", "noalloc.hip"]
 
 F32, I32, BF16 = 0, 1, 2
 DT_NAME = {F32: "f32", I32: "i32", BF16: "bf16"}

@@ -246,6 +246,10 @@ int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table
     } else {
         int rc = pk_machine_query(device, &m);
         if (rc != PK_OK) return rc;
+        // the library's set-up on this device: the workspace address of the
+        // allocation-free entry point
+        rc = noalloc_setup(device);
+        if (rc != PK_OK) return rc;
     }
     if (m.wave <= 0 || m.cu_count <= 0 || m.max_threads_block <= 0)
         return fail(PK_ERR_INVALID_ARG, "machine descriptor has non-positive wave, CU count or thread limit");

@@ -164,6 +164,10 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
 // rows read element by element), or null.
 const KernelEntry *element_twin(const KernelEntry &e);
 
+// Looks up, once per device and with that device current, the device address
+// of the allocation-free entry point's workspace (noalloc.hip).
+int noalloc_setup(int device);
+
 // The several-steps 1D Jacobi instance of (dtype, bx, s), or null.
 const KernelEntry *find_jacobi_fused(int dtype, int64_t bx, int64_t s);
 

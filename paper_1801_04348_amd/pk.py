@@ -658,8 +658,9 @@ def _grouped_sigs(L):
     L.pk_grouped_plan_destroy.argtypes = [vp]
     L.pk_grouped_plan_destroy.restype = None
     L.pk_matmul_batched.argtypes = [vp, i32, ctypes.c_int32] + arrs + [ctypes.POINTER(pk_params), vp]
+    L.pk_matmul_batched_noalloc.argtypes = [vp, i32, ctypes.c_int32] + arrs + [ctypes.POINTER(pk_params), vp]
     for n in ("pk_grouped_plan_create", "pk_grouped_plan_run", "pk_grouped_plan_capture", "pk_grouped_plan_replay",
-              "pk_grouped_plan_info", "pk_grouped_plan_kernel", "pk_matmul_batched"):
+              "pk_grouped_plan_info", "pk_grouped_plan_kernel", "pk_matmul_batched", "pk_matmul_batched_noalloc"):
         getattr(L, n).restype = i32
     L._grouped_sigs = True
 
@@ -722,3 +723,12 @@ def pk_matmul_batched(tbl: Table, dtype, As, Bs, Cs, params=None, stream=None):
     ps = (pk_params * G)(*params) if params is not None else None
     _check(L.pk_matmul_batched(tbl.handle, _dt(dtype), G, *arrs, ps, _stream(stream)))
 
+
+def pk_matmul_batched_noalloc(tbl: Table, dtype, As, Bs, Cs, params=None, stream=None):
+    """pk_matmul_batched without allocation: the launch's descriptors go to
+    the library's per-device workspace (4 MiB); returns after the work."""
+    L = lib()
+    _grouped_sigs(L)
+    G, arrs = _grouped_arrays(As, Bs, Cs, dtype)
+    ps = (pk_params * G)(*params) if params is not None else None
+    _check(L.pk_matmul_batched_noalloc(tbl.handle, _dt(dtype), G, *arrs, ps, _stream(stream)))
