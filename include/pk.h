@@ -103,6 +103,7 @@ typedef struct {
 #define PK_MFMA_GROUPED 2
 #define PK_MFMA_ELEMENT 4 /* internal: the twin of a program that reads rows element by element */
 #define PK_MFMA_MIXED 8   /* internal: a grouped kernel running a different tile program per product */
+#define PK_MFMA_SPLIT 16  /* internal: the form of a program that runs shares of K (pk_params.ks > 1) */
 
 /* A leaf choice together with its program parameters E.
  *   family  - PK_FAMILY_*
@@ -125,8 +126,9 @@ typedef struct {
  *   which the shares' sums enter C varies from run to run (the result stays
  *   within the float32 bound; small-integer inputs stay exact).  ks is a
  *   launch parameter, not a point of the case table: it changes no resource
- *   counter (the same instance runs every ks).  Programs of more than 512
- *   work-items are not split (PK_ERR_INVALID_ARG). 
+ *   counter (the same program runs every ks, in a split form compiled
+ *   beside it).  Programs of more than 512 work-items, and the single-stage
+ *   float32 programs of 512, are not split (PK_ERR_INVALID_ARG). 
  * Transposition family: bx = work-items along the columns of A (the paper's
  *   B1), by = work-items along its rows (B0), s = elements per work-item (s);
  *   a workgroup moves a (by * s) x bx tile of A.

@@ -50,6 +50,7 @@ MFMA_SINGLE = 1
 MFMA_GROUPED = 2
 MFMA_ELEMENT = 4
 MFMA_MIXED = 8
+MFMA_SPLIT = 16
 # the mixed grouped kernels' tile programs (csrc/kernels/kargs.hpp kMixedTile,
 # in the same order) and K tiles
 MIXED_TILES = [(64, 64), (128, 64), (64, 128), (128, 128)]
@@ -146,6 +147,13 @@ def instances():
                              lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn)
                 entry["attrs"] = mfma_reg_cap(dt, 64 * wm * wn, stages, "wide", bm, bn)
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
+                # the split-along-K form of the wide program (workgroups of up
+                # to 512 work-items; not the single-stage float32 programs of
+                # 512, whose 128-register cap it would exceed)
+                if 64 * wm * wn <= 512 and not (dt == F32 and 64 * wm * wn == 512 and stages == 1):
+                    body_sk = "pkk::%s<%d, %d, %d, %d, %d, %d, true, true>(a);" % (fn, bm, bn, bk, wm, wn, stages)
+                    entry_sk = dict(entry, variant=entry["variant"] | MFMA_SPLIT)
+                    out.append(("mfma_%s_%d_sk" % (DT_NAME[dt], bm * 1000 + bn), name + "_sk", body_sk, entry_sk))
                 # the element-load twin, launched for rows not aligned for 16-byte
                 # loads (none for the largest bf16 tile, whose twin would spill)
                 if dt == BF16 and bm * bn >= 256 * 256:

@@ -65,11 +65,10 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
     }
     const KernelEntry *e = find_instance(pin->family, variant, dtype, pt);
     if (!e) return fail(PK_ERR_NOT_INSTANTIATED, "no compiled instance for these parameters");
-    if (pin->ks < 0 || pin->ks > kMaxSplits ||
-        (pin->ks > 1 && (pin->family != PK_FAMILY_MFMA || e->threads > pkk::kSplittableThreads)))
+    if (pin->ks < 0 || pin->ks > kMaxSplits || (pin->ks > 1 && !split_twin(*e)))
         return fail(PK_ERR_INVALID_ARG, "ks: shares of K are 0 or 1 (none), or up to " + std::to_string(kMaxSplits) +
-                                            " for MFMA programs of up to " +
-                                            std::to_string(pkk::kSplittableThreads) + " work-items");
+                                            " for the MFMA programs that have a split form (up to " +
+                                            std::to_string(pkk::kSplittableThreads) + " work-items)");
     *pout = *pin;
     point_params(pin->family, pt, pout);
     pout->ks = pin->ks > 1 ? pin->ks : 0;
@@ -161,13 +160,16 @@ bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb
 
 int launch(const pk_machine &m, const KernelEntry &e0, const MmArgs &args, hipStream_t stream) {
     const KernelEntry *pe = &e0;
-    if (e0.family == PK_FAMILY_MFMA && !args.vec) {  // rows not aligned: the element-load twin
+    MmArgs a = args;
+    if (e0.family != PK_FAMILY_MFMA || a.K <= 0 || a.splits < 2) a.splits = 0;
+    if (e0.family == PK_FAMILY_MFMA && !args.vec) {  // rows not aligned: the element-load twin (it splits in place)
         pe = element_twin(e0);
         if (!pe) return fail(PK_ERR_NOT_INSTANTIATED, std::string("no element-load twin of ") + e0.name);
+    } else if (a.splits > 1) {  // shares of K: the wide program's split form
+        pe = split_twin(e0);
+        if (!pe) return fail(PK_ERR_INVALID_ARG, std::string("no split form of ") + e0.name);
     }
     const KernelEntry &e = *pe;
-    MmArgs a = args;
-    if (e.family != PK_FAMILY_MFMA || a.K <= 0 || a.splits < 2) a.splits = 0;
     const int64_t grid = launch_grid(m, e, args.M, args.N) * std::max(a.splits, 1);
     if (grid <= 0) return PK_OK;
     if (grid > 0x7fffffff) return fail(PK_ERR_INVALID_ARG, "grid too large");

@@ -132,10 +132,13 @@ int64_t table_regs(int family, int variant, int dtype, const std::vector<int64_t
     const KernelResources *r = resources_of(e->name);
     if (!r) return missing_table_value;
     int64_t v = regs_per_block(*r, e->threads, wave);
-    // an MFMA program runs as its element-load twin on unaligned rows: the
-    // program needs the larger of the two register allocations
-    if (const KernelEntry *t = element_twin(*e))
-        if (const KernelResources *rt = resources_of(t->name)) v = std::max(v, regs_per_block(*rt, t->threads, wave));
+    // an MFMA program runs as its element-load twin on unaligned rows, and in
+    // its split form when split along K: the program needs the largest of
+    // the register allocations
+    for (const KernelEntry *t : {element_twin(*e), split_twin(*e)})
+        if (t)
+            if (const KernelResources *rt = resources_of(t->name))
+                v = std::max(v, regs_per_block(*rt, t->threads, wave));
     return v;
 }
 
@@ -470,6 +473,15 @@ const KernelEntry *element_twin(const KernelEntry &e) {
     if (e.family != PK_FAMILY_MFMA || (e.variant & (PK_MFMA_GROUPED | PK_MFMA_ELEMENT))) return nullptr;
     for (const auto &t : registry())
         if (t.family == PK_FAMILY_MFMA && t.dtype == e.dtype && t.variant == (e.variant | PK_MFMA_ELEMENT) &&
+            t.bm == e.bm && t.bn == e.bn && t.bk == e.bk && t.wm == e.wm && t.wn == e.wn)
+            return &t;
+    return nullptr;
+}
+
+const KernelEntry *split_twin(const KernelEntry &e) {
+    if (e.family != PK_FAMILY_MFMA || (e.variant & (PK_MFMA_GROUPED | PK_MFMA_ELEMENT | PK_MFMA_SPLIT))) return nullptr;
+    for (const auto &t : registry())
+        if (t.family == PK_FAMILY_MFMA && t.dtype == e.dtype && t.variant == (e.variant | PK_MFMA_SPLIT) &&
             t.bm == e.bm && t.bn == e.bn && t.bk == e.bk && t.wm == e.wm && t.wn == e.wn)
             return &t;
     return nullptr;

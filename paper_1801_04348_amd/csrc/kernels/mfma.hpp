@@ -89,7 +89,8 @@ template <int BM, int BN, int BK, int STAGES> struct F32Lds {
 };
 
 // One BM x BN output tile at (row0, col0) over the K steps [kt0, kt1) (of
-// BK each), its LDS tiles at `lds` (F32Lds::floats floats).  `vec`: the rows
+// BK each), its A tiles at As0 (STAGES x F32Lds::A floats) and its B tiles
+// at Bs0 (STAGES x F32Lds::B floats) in LDS.  `vec`: the rows
 // of A and B are 16-byte aligned, so interior tiles may use 16-byte loads.
 // With a.splits > 1 the tile's sum over its K steps is added to C atomically
 // (C holds zeros or the sums of the other shares of K); otherwise it is
@@ -98,7 +99,8 @@ template <int BM, int BN, int BK, int STAGES> struct F32Lds {
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
 __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, const int col0, const bool vec,
-                                              float *lds, const int kt0, const int kt1) {
+                                              float *const As0, float *const Bs0, const int kt0,
+                                              const int kt1) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
@@ -110,13 +112,14 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
     static_assert(A4 >= 1 && B4 >= 1 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tile loads");
     static_assert(BK % 8 == 0, "BK");
 
-    float *const As0 = lds;                 // stage st: As0 + st * L::A
-    float *const Bs0 = lds + STAGES * L::A;  // stage st: Bs0 + st * L::B
 
-    const gptr<float> __restrict__ A = (gptr<float>)a.A;
-    const gptr<float> __restrict__ B = (gptr<float>)a.B;
+    // the operands from this workgroup's first K step on: its steps run from
+    // 0, and K counts what is left of the product from there (the same loops
+    // and guards serve a whole product and a share of one)
+    const gptr<float> __restrict__ A = (gptr<float>)a.A + kt0 * BK;
+    const gptr<float> __restrict__ B = (gptr<float>)a.B + (int64_t)kt0 * BK * a.ldb;
     const gmut<float> __restrict__ C = (gmut<float>)a.C;
-    const int M = a.M, N = a.N, K = a.K;
+    const int M = a.M, N = a.N, K = a.K - kt0 * BK;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -284,38 +287,39 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         }
     };
 
-    // the K steps [kt0, kt1) of this workgroup: all of K, or its share of a
-    // product split along K.  Leading steps that need no guards: all of them
-    // for an interior tile on aligned rows, except a partial last one.
-    const int KF = (vec && interior) ? max(kt0, min(K / BK, kt1)) : kt0;
+    // the workgroup's KT K steps (all of K, or its share of a product split
+    // along K).  Leading steps that need no guards: all of them for an
+    // interior tile on aligned rows, except a partial last one.
+    const int KT = kt1 - kt0;
+    const int KF = (vec && interior) ? min(K / BK, KT) : 0;
     if (STAGES == 2) {
-        if (kt1 > kt0) {
-            if (KF > kt0)
-                gload_fast(kt0 * BK);
+        if (KT > 0) {
+            if (KF > 0)
+                gload_fast(0);
             else
-                gload(kt0 * BK);
+                gload(0);
             sstore(0);
         }
         __syncthreads();
-        int kt = kt0;
+        int kt = 0;
         // steps whose successor is unguarded too: a loop without branches, so
         // the next step's loads stay in flight while this step multiplies
         for (; kt + 1 < KF; ++kt) {
-            const int cur = (kt - kt0) & 1;
+            const int cur = kt & 1;
             gload_fast((kt + 1) * BK);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
         }
-        for (; kt < kt1; ++kt) {
-            const int cur = (kt - kt0) & 1;
-            if (kt + 1 < kt1) gload((kt + 1) * BK);
+        for (; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) gload((kt + 1) * BK);
             compute(cur);
-            if (kt + 1 < kt1) sstore(cur ^ 1);
+            if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
-        int kt = kt0;
+        int kt = 0;
         for (; kt < KF; ++kt) {
             gload_fast(kt * BK);
             __syncthreads();
@@ -323,7 +327,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             __syncthreads();
             compute(0);
         }
-        for (; kt < kt1; ++kt) {
+        for (; kt < KT; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
@@ -361,11 +365,13 @@ template <int BM, int BN, int BK, int STAGES> struct Bf16Lds {
     static constexpr int elems = STAGES * (A + B);
 };
 
-// bfloat16 tile, its LDS tiles at `lds` (Bf16Lds::elems elements); `vec`: A
-// rows 16-byte aligned and B rows 4-byte aligned.
+// bfloat16 tile, its A tiles at As0 (STAGES x Bf16Lds::A elements) and its
+// transposed B tiles at Bt0 (STAGES x Bf16Lds::B); `vec`: A rows 16-byte
+// aligned and B rows 4-byte aligned.
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
 __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec,
-                                               unsigned short *lds, const int kt0, const int kt1) {
+                                               unsigned short *const As0, unsigned short *const Bt0,
+                                               const int kt0, const int kt1) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
@@ -377,13 +383,12 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
     static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && ((BK / 8) * (BN / 2)) % NT == 0, "tile loads");
     static_assert(BK % 32 == 0, "BK");
 
-    unsigned short *const As0 = lds;                 // stage st: As0 + st * L::A
-    unsigned short *const Bt0 = lds + STAGES * L::A;  // stage st: Bt0 + st * L::B
 
-    const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A;
-    const gptr<unsigned short> __restrict__ B = (gptr<unsigned short>)a.B;
+    // from this workgroup's first K step on, as in the float32 tile
+    const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A + kt0 * BK;
+    const gptr<unsigned short> __restrict__ B = (gptr<unsigned short>)a.B + (int64_t)kt0 * BK * a.ldb;
     const gmut<float> __restrict__ C = (gmut<float>)a.C;
-    const int M = a.M, N = a.N, K = a.K;
+    const int M = a.M, N = a.N, K = a.K - kt0 * BK;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -556,38 +561,39 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         }
     };
 
-    // the K steps [kt0, kt1) of this workgroup: all of K, or its share of a
-    // product split along K.  Leading steps that need no guards: all of them
-    // for an interior tile on aligned rows, except a partial last one.
-    const int KF = (vec && interior) ? max(kt0, min(K / BK, kt1)) : kt0;
+    // the workgroup's KT K steps (all of K, or its share of a product split
+    // along K).  Leading steps that need no guards: all of them for an
+    // interior tile on aligned rows, except a partial last one.
+    const int KT = kt1 - kt0;
+    const int KF = (vec && interior) ? min(K / BK, KT) : 0;
     if (STAGES == 2) {
-        if (kt1 > kt0) {
-            if (KF > kt0)
-                gload_fast(kt0 * BK);
+        if (KT > 0) {
+            if (KF > 0)
+                gload_fast(0);
             else
-                gload(kt0 * BK);
+                gload(0);
             sstore(0);
         }
         __syncthreads();
-        int kt = kt0;
+        int kt = 0;
         // steps whose successor is unguarded too: a loop without branches, so
         // the next step's loads stay in flight while this step multiplies
         for (; kt + 1 < KF; ++kt) {
-            const int cur = (kt - kt0) & 1;
+            const int cur = kt & 1;
             gload_fast((kt + 1) * BK);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
         }
-        for (; kt < kt1; ++kt) {
-            const int cur = (kt - kt0) & 1;
-            if (kt + 1 < kt1) gload((kt + 1) * BK);
+        for (; kt < KT; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < KT) gload((kt + 1) * BK);
             compute(cur);
-            if (kt + 1 < kt1) sstore(cur ^ 1);
+            if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
-        int kt = kt0;
+        int kt = 0;
         for (; kt < KF; ++kt) {
             gload_fast(kt * BK);
             __syncthreads();
@@ -595,7 +601,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             __syncthreads();
             compute(0);
         }
-        for (; kt < kt1; ++kt) {
+        for (; kt < KT; ++kt) {
             gload(kt * BK);
             __syncthreads();
             sstore(0);
@@ -645,31 +651,38 @@ __device__ __forceinline__ void k_share(const MmArgs &a, int64_t tiles, int64_t 
 // WIDE: 16-byte loads along aligned rows; the element-load twin (WIDE =
 // false) is a kernel of its own, so neither carries the other's load path.
 // The twins of workgroups up to 256 work-items load at chosen addresses (all
-// their steps take the edge path).
-template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
+// their steps take the edge path).  SPLIT: the kernel runs shares of K
+// (a.splits > 1); the wide program's split form is a kernel of its own too,
+// so the whole-product kernel carries none of it (the element-load twins,
+// already off the fast path, split in place).
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true, bool SPLIT = !WIDE>
 __device__ __forceinline__ void mfma_f32(const MmArgs &a0) {
     MmArgs a = a0;
-    if constexpr (64 * WM * WN > kSplittableThreads) a.splits = 0;
+    if constexpr (!SPLIT || 64 * WM * WN > kSplittableThreads) a.splits = 0;
     int tm, tn;
-    __shared__ __attribute__((aligned(16))) float lds[F32Lds<BM, BN, BK, STAGES>::floats];
+    using L = F32Lds<BM, BN, BK, STAGES>;
+    __shared__ __attribute__((aligned(16))) float As[STAGES * L::A];
+    __shared__ __attribute__((aligned(16))) float Bs[STAGES * L::B];
     int64_t b = blockIdx.x;
     int kt0, kt1;
     k_share<BK>(a, (int64_t)((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), &b, &kt0, &kt1);
     tile_of(b, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, lds, kt0, kt1);
+    mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, As, Bs, kt0, kt1);
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true>
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE = true, bool SPLIT = !WIDE>
 __device__ __forceinline__ void mfma_bf16(const MmArgs &a0) {
     MmArgs a = a0;
-    if constexpr (64 * WM * WN > kSplittableThreads) a.splits = 0;
+    if constexpr (!SPLIT || 64 * WM * WN > kSplittableThreads) a.splits = 0;
     int tm, tn;
-    __shared__ __attribute__((aligned(16))) unsigned short lds[Bf16Lds<BM, BN, BK, STAGES>::elems];
+    using L = Bf16Lds<BM, BN, BK, STAGES>;
+    __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
+    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES * L::B];
     int64_t b = blockIdx.x;
     int kt0, kt1;
     k_share<BK>(a, (int64_t)((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), &b, &kt0, &kt1);
     tile_of(b, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, lds, kt0, kt1);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, As, Bt, kt0, kt1);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
@@ -701,27 +714,31 @@ struct GroupWalk {
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
-    __shared__ __attribute__((aligned(16))) float lds[F32Lds<BM, BN, BK, STAGES>::floats];
+    using L = F32Lds<BM, BN, BK, STAGES>;
+    __shared__ __attribute__((aligned(16))) float As[STAGES * L::A];
+    __shared__ __attribute__((aligned(16))) float Bs[STAGES * L::B];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
         const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
-        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, lds, 0, (d.K + BK - 1) / BK);
+        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
     }
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
-    __shared__ __attribute__((aligned(16))) unsigned short lds[Bf16Lds<BM, BN, BK, STAGES>::elems];
+    using L = Bf16Lds<BM, BN, BK, STAGES>;
+    __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
+    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES * L::B];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
         const int64_t local = w.t - d.tile_start;
         const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
-        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, lds, 0, (d.K + BK - 1) / BK);
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bt, 0, (d.K + BK - 1) / BK);
     }
 }
 
@@ -746,7 +763,9 @@ template <int P, int STAGES>
 __device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int64_t local, int tiles_n, float *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
     const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
-    mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds, 0,
+    using L = F32Lds<BM, BN, kMixedBk[0], STAGES>;
+    mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
+                                                           lds + STAGES * L::A, 0,
                                                            (a.K + kMixedBk[0] - 1) / kMixedBk[0]);
 }
 
@@ -754,7 +773,9 @@ template <int P, int STAGES>
 __device__ __forceinline__ void mixed_bf16_tile(const MmArgs &a, int64_t local, int tiles_n, unsigned short *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
     const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
-    mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds, 0,
+    using L = Bf16Lds<BM, BN, kMixedBk[2], STAGES>;
+    mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
+                                                            lds + STAGES * L::A, 0,
                                                             (a.K + kMixedBk[2] - 1) / kMixedBk[2]);
 }
 

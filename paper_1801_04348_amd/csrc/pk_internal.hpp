@@ -163,6 +163,9 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
 // The element-load twin of a single-launch MFMA instance (same program,
 // rows read element by element), or null.
 const KernelEntry *element_twin(const KernelEntry &e);
+// The split-along-K form of a single-launch MFMA instance's wide program, or
+// null (programs that are never split).
+const KernelEntry *split_twin(const KernelEntry &e);
 
 // Looks up, once per device and with that device current, the device address
 // of the allocation-free entry point's workspace (noalloc.hip).

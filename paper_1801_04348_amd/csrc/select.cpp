@@ -94,7 +94,7 @@ double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes
 
 std::vector<int> k_splits(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K) {
     std::vector<int> out;
-    if (e.family != PK_FAMILY_MFMA || e.bk <= 0 || e.threads > pkk::kSplittableThreads) return out;
+    if (e.family != PK_FAMILY_MFMA || e.bk <= 0 || !split_twin(e)) return out;
     const int64_t tiles = ((M + e.tile_m - 1) / e.tile_m) * ((N + e.tile_n - 1) / e.tile_n);
     const int64_t ksteps = (K + e.bk - 1) / e.bk;
     const int64_t ncu = std::max<int32_t>(m.cu_count, 1);

@@ -41,6 +41,7 @@ PK_VALU_GRAN, PK_VALU_NOLDS = 1, 2
 PK_POLYDIV_FUSED, PK_POLYDIV_WIDE = 4, 8
 PK_JACOBI_FUSED = 4
 PK_MFMA_SINGLE = 1
+PK_MFMA_SPLIT = 16  # internal: the form of a program that runs shares of K
 PK_POLICY_CASE, PK_POLICY_LEARNED, PK_POLICY_EXHAUSTIVE = 0, 1, 2
 
 DTYPES = {"f32": PK_F32, "i32": PK_I32, "bf16": PK_BF16}

@@ -403,12 +403,16 @@ def test_case_pick_minimises_the_estimate():
                         cands.append(pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4]))
                         # the shares of K offered: fewer tiles than two per
                         # compute unit at the previous count, two K steps a share
+                        # (programs with a split form: the library refuses the others)
                         tiles = -(-M // pt[0]) * -(-N // pt[1])
                         ks = 2
-                        while (ks <= 16 and 2 * ks <= -(-K // pt[2]) and tiles * (ks // 2) < 2 * ncu
-                               and 64 * pt[3] * pt[4] <= 512):
-                            cands.append(pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4],
-                                                   ks=ks))
+                        while ks <= 16 and 2 * ks <= -(-K // pt[2]) and tiles * (ks // 2) < 2 * ncu:
+                            q = pk.params(family=fam, bm=pt[0], bn=pt[1], bk=pt[2], wm=pt[3], wn=pt[4], ks=ks)
+                            try:
+                                pk.pk_kernel_name(t, q, dtype)
+                            except pk.PkError:
+                                break
+                            cands.append(q)
                             ks *= 2
             est = [pk.pk_estimate(t, p, dtype, M, N, K) for p in cands]
             assert all(e > 0 for e in est)
@@ -423,7 +427,8 @@ def test_case_pick_minimises_the_estimate():
 def test_every_mfma_program_has_an_element_load_twin(gfx_desc):
     # the twin reads unaligned rows; the program's register symbol covers both
     inst = {e["name"]: e for e in gfx_desc["instances"]}
-    single = [e for e in gfx_desc["instances"] if e["family"] == en.MFMA and not e["variant"] & (2 | en.ELEMENT)]
+    single = [e for e in gfx_desc["instances"]
+              if e["family"] == en.MFMA and not e["variant"] & (2 | en.ELEMENT | pk.PK_MFMA_SPLIT)]
     for e in single:
         twin = inst.get(e["name"] + "_el")
         if e["dtype"] == 2 and e["bm"] * e["bn"] >= 256 * 256:
@@ -431,6 +436,12 @@ def test_every_mfma_program_has_an_element_load_twin(gfx_desc):
             continue
         assert twin is not None and twin["variant"] == e["variant"] | en.ELEMENT, e["name"]
         assert twin["lds_bytes"] == e["lds_bytes"] and twin["scratch"] == 0
+        # the split form (shares of K) of a wide program up to 512 work-items
+        split = inst.get(e["name"] + "_sk")
+        if split is not None:
+            assert e["threads"] <= 512 and split["variant"] == e["variant"] | pk.PK_MFMA_SPLIT
+            assert split["lds_bytes"] == e["lds_bytes"] and split["scratch"] == 0
+    assert sum(1 for e in gfx_desc["instances"] if e["variant"] & pk.PK_MFMA_SPLIT) > 0
     data = en.InstanceData(gfx_desc["instances"])
     for part in gfx_desc["parts"]:
         if part["family"] != en.MFMA:
