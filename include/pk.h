@@ -277,10 +277,10 @@ int pk_measure(const pk_table *tbl, pk_dtype dtype, const void *A, int64_t lda, 
  *   both < 0            looks the leaf up at E.
  * M == 0 or N == 0 is a no-op; K == 0 writes zeros (or leaves C unchanged
  * when accumulating).  MFMA programs load 16 bytes at a time along rows that
- * are aligned for it (f32: A and B 16-byte aligned, lda and ldb multiples of
- * 4; bf16: A 16-byte aligned with lda a multiple of 8, B 4-byte aligned with
- * ldb even) and element by element otherwise -- the same arithmetic in the
- * same order, so the result does not depend on the alignment.  One program
+ * are aligned for it (A and B 16-byte aligned; lda and ldb multiples of 4
+ * for f32, of 8 for bf16) and element by element otherwise -- the same
+ * arithmetic in the same order, so the result does not depend on the
+ * alignment.  One program
  * has no element-load form (the bfloat16 256 x 256 x 64 tile, whose
  * element-load kernel would spill); given it with operands whose rows are not
  * aligned, the call runs the CASE choice for those operands instead.

@@ -19,7 +19,7 @@ enumeration over a grid of machines and the whole program-parameter domain:
 * MFMA family: program parameters bm, bn, bk, wm, wn; programs {} (two LDS
   stages) and {single} (one).  One stage holds, in float32, an A tile bm x
   (bk + 4) and a B tile bk x (bn + 4); in bfloat16 an A tile bm x (bk + 8) and
-  a transposed B tile bn x (bk + 8); threads: 64 * wm * wn.
+  a B tile bk x (bn + 32); threads: 64 * wm * wn.
 * Transposition family (Section 5.2, Fig. 7): program parameters bx (the
   paper's B1), by (B0), s; programs as in the VALU family; the cached program
   holds one (by * s') x bx tile padded by one element per row: 4 * (by * s')
@@ -128,7 +128,7 @@ def mfma_lds(dtype: int, variant: int, bm: int, bn: int, bk: int) -> int:
     if dtype == F32:
         one = 4 * (bm * (bk + 4) + bk * (bn + 4))
     else:
-        one = 2 * (bm * (bk + 8) + bn * (bk + 8))
+        one = 2 * (bm * (bk + 8) + bk * (bn + 32))
     return stages * one
 
 
@@ -307,7 +307,7 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
         strategies = [co.Strategy("single", False, frozenset({"r_Z", "r_V"}))]
         names = {0: "rho_two_stage", SINGLE: "rho_one_stage"}
         one = (co.parse_poly("4*(bm*(bk+4) + bk*(bn+4))") if dtype == F32
-               else co.parse_poly("2*(bm*(bk+8) + bn*(bk+8))"))
+               else co.parse_poly("2*(bm*(bk+8) + bk*(bn+32))"))
 
         def lds_poly(applied):
             return one if "single" in applied else co.Poly.const(2) * one

@@ -101,7 +101,7 @@ def mfma_reg_cap(dt, threads, stages, kind, bm=0, bn=0):
 def mfma_lds(dtype, bm, bn, bk, stages):
     if dtype == F32:
         return stages * 4 * (bm * (bk + 4) + bk * (bn + 4))
-    return stages * 2 * (bm + bn) * (bk + 8)
+    return stages * 2 * (bm * (bk + 8) + bk * (bn + 32))
 
 
 def instances():

@@ -148,14 +148,12 @@ int64_t launch_grid(const pk_machine &m, const KernelEntry &e, int64_t M, int64_
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Rows aligned for the MFMA programs' wide loads: 16-byte loads along the
-// rows of A (lda a multiple of 4 f32 / 8 bf16 elements) and of B (f32), or
-// 4-byte column pairs of B (bf16).  Otherwise the programs read element by
-// element (same arithmetic, same summation order).
+// rows of A and B (leading dimensions multiples of 4 f32 / 8 bf16 elements,
+// 16-byte aligned bases).  Otherwise the programs read element by element
+// (same arithmetic, same summation order).
 bool wide_rows(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb) {
     const int64_t vec = dtype == PK_BF16 ? 8 : 4;
-    if (!aligned16(A) || lda % vec != 0) return false;
-    if (dtype == PK_BF16) return ((uintptr_t)B & 3u) == 0 && ldb % 2 == 0;
-    return aligned16(B) && ldb % 4 == 0;
+    return aligned16(A) && lda % vec == 0 && aligned16(B) && ldb % vec == 0;
 }
 
 int launch(const pk_machine &m, const KernelEntry &e0, const MmArgs &args, hipStream_t stream) {

@@ -259,7 +259,10 @@ std::string machine_fingerprint(const pk_machine &m) {
 //   6    LDS bytes / 65536
 //   7    estimated occupancy: resident wavefronts per CU / maximum
 //   8    tile padding efficiency: M N / (padded M) (padded N)
-//   9    wave quantisation efficiency: tiles / (rounds * resident slots)
+//   9    wave quantisation efficiency: workgroups / (rounds * resident slots)
+//   10   1 where the operands' rows allow the MFMA programs' 16-byte loads
+//        (else the element-load twin runs), 0 otherwise
+//   11   ln(shares of K): 0 for a product not split along K
 void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, int ks,
               float *f) {
     const int wave = m.wave > 0 ? m.wave : 64;

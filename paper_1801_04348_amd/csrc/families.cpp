@@ -326,9 +326,9 @@ Family matmul_family(int family, int dtype) {
         else
             for (const auto &p : kMfmaBf16) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
         // one stage: f32  4 * (bm * (bk + 4) + bk * (bn + 4))
-        //            bf16 2 * (bm + bn) * (bk + 8)   (B stored transposed)
+        //            bf16 2 * (bm * (bk + 8) + bk * (bn + 32))
         Poly stage = dtype == PK_F32 ? P(4) * (S(bm) * (S(bk) + P(4)) + S(bk) * (S(bn) + P(4)))
-                                     : P(2) * (S(bm) + S(bn)) * (S(bk) + P(8));
+                                     : P(2) * (S(bm) * (S(bk) + P(8)) + S(bk) * (S(bn) + P(32)));
         CounterDef rz{"r_Z", false, m.Z, nullptr};
         rz.value = [=](uint32_t ap) { return (ap & PK_MFMA_SINGLE) ? stage : P(2) * stage; };
         CounterDef rv{"r_V", false, m.V, nullptr};

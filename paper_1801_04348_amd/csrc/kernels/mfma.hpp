@@ -9,9 +9,9 @@
 // each wavefront owns (BM/WM) x (BN/WN), i.e. TM x TN blocks of 32x32
 // accumulators (16 per lane each).  K advances in steps of BK through LDS:
 //   float32:  As[BM][BK+4]   (k contiguous),   Bs[BK][BN+4]   (n contiguous)
-//   bfloat16: As[BM][BK+8]   (k contiguous),   Bt[BN][BK+8]   (B transposed,
-//             k contiguous, so each lane reads its 8 k values with one 16-byte
-//             LDS load)
+//   bfloat16: As[BM][BK+8]   (k contiguous),   Bs[BK][BN+32]  (n contiguous;
+//             each lane gathers its 8 k values of a column with two of
+//             gfx950's transposing LDS reads)
 // STAGES = 2 double-buffers the tiles (one barrier per K step: the next tile is
 // fetched from global memory into registers while the current one is
 // consumed); STAGES = 1 keeps one buffer and two barriers per step, as in the
@@ -22,10 +22,10 @@
 // so a lane's operands are contiguous in LDS.  The set of products summed is
 // unchanged.
 //
-// Global loads are 16 bytes wide (4 bytes for the column pairs of a bfloat16
-// B), so the leading dimensions must keep rows aligned (lda, ldb multiples of
-// 4 floats / 8 bfloat16 and 16-byte aligned bases); the host checks this and
-// otherwise launches the element-load twin.  Tiles crossing the matrix edge
+// Global loads are 16 bytes wide, so the leading dimensions must keep rows
+// aligned (lda, ldb multiples of 4 floats / 8 bfloat16 and 16-byte aligned
+// bases); the host checks this and otherwise launches the element-load twin.
+// Tiles crossing the matrix edge
 // keep the wide loads: they clamp the rows of A and the column chunks of B
 // they read to the last chunk in range (results outside C are never stored),
 // zero the elements of A at k >= K, read the rows of B at k >= K from a block
@@ -126,6 +126,11 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
     const int r = lane & 31, h = lane >> 5;
 
     const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
+    // a wavefront whose part of an edge tile lies wholly outside C has nothing
+    // to multiply (it still loads and stores its share of the operand tiles);
+    // skipping its products frees the matrix unit for the other wavefronts
+    // (not in programs of 1024 work-items, whose registers are at the limit)
+    const bool idle = NT <= 512 && ((row0 + wm * WTM >= M) || (col0 + wn * WTN >= N));
 
     f32x16 acc[TM][TN];
 #pragma unroll
@@ -314,7 +319,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
-            compute(cur);
+            if (!idle) compute(cur);
             if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
@@ -332,7 +337,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
             __syncthreads();
             sstore(0);
             __syncthreads();
-            compute(0);
+            if (!idle) compute(0);
         }
     }
 
@@ -358,31 +363,44 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
 
 // ------------------------------------------------------------------ bfloat16
 // LDS elements (16-bit) of a bfloat16 tile program: STAGES x (A tile BM x
-// (BK + 8)), then STAGES x (B transposed, BN x (BK + 8)).
+// (BK + 8)), then STAGES x (B tile BK x (BN + 32), row-major as in memory).
+// A B row spans BN + 32 elements, 64 bytes past a multiple of 256 for every BN
+// here: the four rows one transposing read touches fall in four different
+// 64-byte quarters of the banks.
 template <int BM, int BN, int BK, int STAGES> struct Bf16Lds {
-    static constexpr int LD_S = BK + 8;
-    static constexpr int A = BM * LD_S, B = BN * LD_S;
+    static constexpr int LD_S = BK + 8, LDB_S = BN + 32;
+    static constexpr int A = BM * LD_S, B = BK * LDB_S;
     static constexpr int elems = STAGES * (A + B);
 };
 
-// bfloat16 tile, its A tiles at As0 (STAGES x Bf16Lds::A elements) and its
-// transposed B tiles at Bt0 (STAGES x Bf16Lds::B); `vec`: A rows 16-byte
-// aligned and B rows 4-byte aligned.
+// The MFMA B operand of lanes [16g, 16g + 16) from a row-major tile in LDS:
+// gfx950's transposing read hands lane i of each group of 16 element i % 4 of
+// the 8 bytes addressed by lane 4j + i / 4, for j = 0..3.  With lane m of the
+// group addressing row m / 4, columns 4 (m % 4) .. + 3, lane i receives
+// column i of four consecutive rows.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ s16x4 lds_read_tr16(const unsigned short *p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4 *)p);
+}
+
+// bfloat16 tile, its A tiles at As0 (STAGES x Bf16Lds::A elements) and its B
+// tiles at Bs0 (STAGES x Bf16Lds::B); `vec`: A and B rows 16-byte aligned.
 template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool EDGE_ADDR>
 __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, const int col0, const bool vec,
-                                               unsigned short *const As0, unsigned short *const Bt0,
+                                               unsigned short *const As0, unsigned short *const Bs0,
                                                const int kt0, const int kt1) {
     constexpr int NT = 64 * WM * WN;
     constexpr int WTM = BM / WM, WTN = BN / WN;
     constexpr int TM = WTM / 32, TN = WTN / 32;
     using L = Bf16Lds<BM, BN, BK, STAGES>;
-    constexpr int LD_S = L::LD_S;                // row stride (elements) of As and Bt
+    constexpr int LD_S = L::LD_S;                // row stride (elements) of the A tiles
+    constexpr int LDB_S = L::LDB_S;              // row stride of the B tiles
     constexpr int A8 = BM * BK / 8 / NT;         // 16-byte loads per work-item per A tile
-    constexpr int B8 = (BK / 8) * (BN / 2) / NT; // (8 k rows x 2 columns) blocks per work-item
+    constexpr int B8 = BK * BN / 8 / NT;         // 16-byte loads per work-item per B tile
     static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
-    static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && ((BK / 8) * (BN / 2)) % NT == 0, "tile loads");
-    static_assert(BK % 32 == 0, "BK");
-
+    static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tile loads");
+    static_assert(BK % 32 == 0 && BN % 8 == 0, "BK, BN");
+    static_assert((LDB_S * 2) % 256 == 64 || (LDB_S * 2) % 256 == 192, "B rows one quarter of the banks apart");
 
     // from this workgroup's first K step on, as in the float32 tile
     const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A + kt0 * BK;
@@ -395,6 +413,11 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
     const int r = lane & 31, h = lane >> 5;
 
     const bool interior = (row0 + BM <= M) && (col0 + BN <= N);
+    // a wavefront whose part of an edge tile lies wholly outside C has nothing
+    // to multiply (it still loads and stores its share of the operand tiles);
+    // skipping its products frees the matrix unit for the other wavefronts
+    // (not in programs of 1024 work-items, whose registers are at the limit)
+    const bool idle = NT <= 512 && ((row0 + wm * WTM >= M) || (col0 + wn * WTN >= N));
 
     f32x16 acc[TM][TN];
 #pragma unroll
@@ -404,8 +427,10 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    u16x8 ra[A8];
-    unsigned int rb[B8][8];  // 8 k rows of a column pair (n, n+1)
+    // work-item f of the workgroup's u-th load: A row f / (BK / 8), its k
+    // chunk (f % (BK / 8)) * 8; B row (k) f / (BN / 8), its column chunk
+    // (f % (BN / 8)) * 8
+    u16x8 ra[A8], rb[B8];
     auto gload_fast = [&](int k0) {  // unguarded, as in the float32 tile
 #pragma unroll
         for (int u = 0; u < A8; ++u) {
@@ -416,13 +441,11 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
             const int f = tid + u * NT;
-            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                rb[u][e] = *reinterpret_cast<gptr<unsigned int>>(B + (int64_t)(k0 + kr + e) * a.ldb + col0 + cp);
+            const int rr = f / (BN / 8), c8 = (f % (BN / 8)) * 8;
+            rb[u] = *reinterpret_cast<gptr<u16x8>>(B + (int64_t)(k0 + rr) * a.ldb + col0 + c8);
         }
     };
-    auto gload = [&](int k0) {  // any K step: as in the float32 tile (chunks of 8 k, column pairs of B)
+    auto gload = [&](int k0) {  // any K step: as in the float32 tile
         if constexpr (!EDGE_ADDR) {
             const bool kfull = (k0 + BK <= K);
 #pragma unroll
@@ -441,25 +464,25 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
             for (int u = 0; u < B8; ++u) {
                 const int f = tid + u * NT;
-                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
-                const int gc = col0 + cp;
+                const int rr = f / (BN / 8), c8 = (f % (BN / 8)) * 8;
+                const int gr = k0 + rr, gc = col0 + c8;
+                if (vec && gr < K && gc + 8 <= N) {
+                    rb[u] = *reinterpret_cast<gptr<u16x8>>(B + (int64_t)gr * a.ldb + gc);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int gr = k0 + kr + e;
-                    if (vec && gr < K && gc + 2 <= N) {
-                        rb[u][e] = *reinterpret_cast<gptr<unsigned int>>(B + (int64_t)gr * a.ldb + gc);
-                    } else {
-                        const unsigned int lo = (gr < K && gc < N) ? B[(int64_t)gr * a.ldb + gc] : 0u;
-                        const unsigned int hi = (gr < K && gc + 1 < N) ? B[(int64_t)gr * a.ldb + gc + 1] : 0u;
-                        rb[u][e] = lo | (hi << 16);
-                    }
+                    for (int e = 0; e < 8; ++e)
+                        rb[u][e] = (gr < K && gc + e < N) ? B[(int64_t)gr * a.ldb + gc + e] : (unsigned short)0;
                 }
             }
             return;
         }
         const gptr<unsigned short> zero = (gptr<unsigned short>)(const void *)kZeroBlock;
         if (vec) {
-            const int klast = (K - 1) & ~7, nlast = (N - 1) & ~1;
+            // aligned rows: 16-byte chunks at chosen addresses.  A rows past M
+            // repeat row M - 1 and B chunks past N the row's last chunk (their
+            // products land outside C); B rows past K read the zero block; the
+            // chunk holding A's k tail is masked
+            const int klast = (K - 1) & ~7, nlast = (N - 1) & ~7;
             if (k0 + BK <= K) {
 #pragma unroll
                 for (int u = 0; u < A8; ++u) {
@@ -485,14 +508,10 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
             for (int u = 0; u < B8; ++u) {
                 const int f = tid + u * NT;
-                const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;  // column pair, first k row
-                const int c = min(col0 + cp, nlast);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int k = k0 + kr + e;
-                    rb[u][e] = *(k < K ? reinterpret_cast<gptr<unsigned int>>(B + (int64_t)k * a.ldb + c)
-                                       : (gptr<unsigned int>)(const void *)kZeroBlock);
-                }
+                const int rr = f / (BN / 8), c8 = (f % (BN / 8)) * 8;
+                const int k = k0 + rr;
+                rb[u] = *(k < K ? reinterpret_cast<gptr<u16x8>>(B + (int64_t)k * a.ldb + min(col0 + c8, nlast))
+                                : (gptr<u16x8>)(const void *)kZeroBlock);
             }
             return;
         }
@@ -510,15 +529,11 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
             const int f = tid + u * NT;
-            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
-            const int c0 = min(col0 + cp, N - 1), c1 = min(col0 + cp + 1, N - 1);
+            const int rr = f / (BN / 8), c8 = (f % (BN / 8)) * 8;
+            const int k = k0 + rr;
+            const gptr<unsigned short> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = k0 + kr + e;
-                const gptr<unsigned short> row = k < K ? B + (int64_t)k * a.ldb : nullptr;
-                const unsigned int lo = *(row ? row + c0 : zero), hi = *(row ? row + c1 : zero);
-                rb[u][e] = lo | (hi << 16);
-            }
+            for (int e = 0; e < 8; ++e) rb[u][e] = *(row ? row + min(col0 + c8 + e, N - 1) : zero);
         }
     };
     auto sstore = [&](int st) {
@@ -531,28 +546,31 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
 #pragma unroll
         for (int u = 0; u < B8; ++u) {
             const int f = tid + u * NT;
-            const int cp = (f % (BN / 2)) * 2, kr = (f / (BN / 2)) * 8;
-            u32x4 lo, hi;  // column cp and cp + 1, 8 k values each
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned int w0 = rb[u][2 * e], w1 = rb[u][2 * e + 1];
-                lo[e] = (w0 & 0xffffu) | (w1 << 16);
-                hi[e] = (w0 >> 16) | (w1 & 0xffff0000u);
-            }
-            *reinterpret_cast<u32x4 *>(&Bt0[st * L::B + cp * LD_S + kr]) = lo;
-            *reinterpret_cast<u32x4 *>(&Bt0[st * L::B + (cp + 1) * LD_S + kr]) = hi;
+            const int rr = f / (BN / 8), c8 = (f % (BN / 8)) * 8;
+            *reinterpret_cast<u16x8 *>(&Bs0[st * L::B + rr * LDB_S + c8]) = rb[u];
         }
     };
+    // lane (r, h) multiplies A row r and B column r over k = h BK/2 + kc + t,
+    // t = 0..7, per MFMA; its B values come from two transposing reads (t =
+    // 0..3, then 4..7): lane m of its group of 16 addresses row m / 4 of the
+    // four, columns 4 (m % 4) .. + 3 of the group's 16 (groups 0 and 2 take
+    // columns 0..15 of the block, 1 and 3 columns 16..31)
+    const int grp = lane >> 4, m16 = lane & 15;
     auto compute = [&](int st) {
         const unsigned short *as = &As0[st * L::A + (wm * WTM + r) * LD_S + h * (BK / 2)];
-        const unsigned short *bs = &Bt0[st * L::B + (wn * WTN + r) * LD_S + h * (BK / 2)];
+        const unsigned short *bs = &Bs0[st * L::B + (h * (BK / 2) + (m16 >> 2)) * LDB_S + wn * WTN +
+                                        16 * (grp & 1) + 4 * (m16 & 3)];
 #pragma unroll
         for (int kc = 0; kc < BK / 2; kc += 8) {
             bf16x8 af[TM], bf[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(as + i * 32 * LD_S + kc);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) bf[j] = *reinterpret_cast<const bf16x8 *>(bs + j * 32 * LD_S + kc);
+            for (int j = 0; j < TN; ++j) {
+                const s16x4 lo = lds_read_tr16(bs + kc * LDB_S + j * 32);
+                const s16x4 hi = lds_read_tr16(bs + (kc + 4) * LDB_S + j * 32);
+                bf[j] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+            }
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -588,7 +606,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
-            compute(cur);
+            if (!idle) compute(cur);
             if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
@@ -606,7 +624,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
             __syncthreads();
             sstore(0);
             __syncthreads();
-            compute(0);
+            if (!idle) compute(0);
         }
     }
 
@@ -677,12 +695,12 @@ __device__ __forceinline__ void mfma_bf16(const MmArgs &a0) {
     int tm, tn;
     using L = Bf16Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
-    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES * L::B];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[STAGES * L::B];
     int64_t b = blockIdx.x;
     int kt0, kt1;
     k_share<BK>(a, (int64_t)((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), &b, &kt0, &kt1);
     tile_of(b, (a.M + BM - 1) / BM, (a.N + BN - 1) / BN, &tm, &tn);
-    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, As, Bt, kt0, kt1);
+    mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, !WIDE && WM * WN < 8>(a, tm * BM, tn * BN, WIDE, As, Bs, kt0, kt1);
 }
 
 // ------------------------------------------------------------------ grouped (persistent)
@@ -719,8 +737,8 @@ __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
     __shared__ __attribute__((aligned(16))) float Bs[STAGES * L::B];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int64_t local = w.t - d.tile_start;
-        const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
+        const int local = (int)(w.t - d.tile_start);  // a product's tiles fit 32 bits
+        const int tm = local / d.tiles_n, tn = local % d.tiles_n;
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
         mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
@@ -731,14 +749,14 @@ template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
     using L = Bf16Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
-    __shared__ __attribute__((aligned(16))) unsigned short Bt[STAGES * L::B];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[STAGES * L::B];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int64_t local = w.t - d.tile_start;
-        const int tm = (int)(local / d.tiles_n), tn = (int)(local % d.tiles_n);
+        const int local = (int)(w.t - d.tile_start);  // a product's tiles fit 32 bits
+        const int tm = local / d.tiles_n, tn = local % d.tiles_n;
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
-        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bt, 0, (d.K + BK - 1) / BK);
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
     }
 }
 
@@ -760,9 +778,9 @@ template <int STAGES> struct MixedLds {
 };
 
 template <int P, int STAGES>
-__device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int64_t local, int tiles_n, float *lds) {
+__device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int local, int tiles_n, float *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
-    const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
+    const int tm = local / tiles_n, tn = local % tiles_n;
     using L = F32Lds<BM, BN, kMixedBk[0], STAGES>;
     mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
                                                            lds + STAGES * L::A, 0,
@@ -770,9 +788,9 @@ __device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int64_t local, i
 }
 
 template <int P, int STAGES>
-__device__ __forceinline__ void mixed_bf16_tile(const MmArgs &a, int64_t local, int tiles_n, unsigned short *lds) {
+__device__ __forceinline__ void mixed_bf16_tile(const MmArgs &a, int local, int tiles_n, unsigned short *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
-    const int tm = (int)(local / tiles_n), tn = (int)(local % tiles_n);
+    const int tm = local / tiles_n, tn = local % tiles_n;
     using L = Bf16Lds<BM, BN, kMixedBk[2], STAGES>;
     mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
                                                             lds + STAGES * L::A, 0,
@@ -785,7 +803,7 @@ __device__ __forceinline__ void grouped_mixed_f32(const GroupArgs &g) {
     __shared__ __attribute__((aligned(16))) float lds[MixedLds<STAGES>::f32];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int64_t local = w.t - d.tile_start;
+        const int local = (int)(w.t - d.tile_start);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();  // the previous tile's LDS reads are done
         switch (d.prog) {
@@ -803,7 +821,7 @@ __device__ __forceinline__ void grouped_mixed_bf16(const GroupArgs &g) {
     __shared__ __attribute__((aligned(16))) unsigned short lds[MixedLds<STAGES>::bf16];
     for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
         const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int64_t local = w.t - d.tile_start;
+        const int local = (int)(w.t - d.tile_start);
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
         __syncthreads();
         switch (d.prog) {

@@ -11,7 +11,8 @@ two), so a rocprofv3 run over it reports the workload's kernels alone:
 
 `grouped`: the 4096 uneven products of the grouped benchmark (M, N, K each
 round(exp(U(ln 16, ln 512))) from seed 0), one plan, run eagerly `reps`
-times.  `dense`: one square product of order n, CASE pick (or --policy).
+times.  `dense`: one square product of order n, CASE pick (or --policy, or
+the MFMA program --program names).
 """
 from __future__ import annotations
 
@@ -61,6 +62,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--policy", default="case", choices=["case", "exhaustive"])
+    ap.add_argument("--program", default=None,
+                    help="dense: run this MFMA program instead of the policy's pick, "
+                         "as bm,bn,bk,wm,wn[,variant] (variant 1: one LDS stage)")
     args = ap.parse_args()
 
     import torch
@@ -96,7 +100,12 @@ def main():
             A = inputs.uniform_f32((n, n), seed=21).cuda()
             B = inputs.uniform_f32((n, n), seed=22).cuda()
         C = torch.empty((n, n), dtype=torch.float32, device="cuda")
-        p = pk.pk_select(tbl, args.dtype, n, n, n, policy)
+        if args.program:
+            v = [int(x) for x in args.program.split(",")]
+            p = pk.params(family=pk.PK_FAMILY_MFMA, bm=v[0], bn=v[1], bk=v[2], wm=v[3], wn=v[4],
+                          variant=v[5] if len(v) > 5 else 0)
+        else:
+            p = pk.pk_select(tbl, args.dtype, n, n, n, policy)
         print("dense %s %d^3: %s" % (args.dtype, n, pk.pk_kernel_name(tbl, p, args.dtype)), flush=True)
 
         def run():
