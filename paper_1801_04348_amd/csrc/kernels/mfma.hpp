@@ -730,19 +730,57 @@ struct GroupWalk {
     }
 };
 
+// Runs tile(d, local) for each tile of the workgroup's walk: d the tile's
+// product, local its tile index within the product (a product's tiles fit 32
+// bits).  The loads a tile's setup waits on are requested a tile early: the
+// next tile's descriptor and the product index of the tile after it are
+// loaded before the current tile runs (their latency otherwise opens every
+// tile, and tiles here run only a few K steps).  The indices are uniform
+// over the workgroup and the map and descriptors do not change while the
+// kernel runs, so they are read as constants (through the scalar cache).
+__device__ __forceinline__ int32_t const_load(const int32_t *p) {
+    return *(const __attribute__((address_space(4))) int32_t *)p;
+}
+
+__device__ __forceinline__ GroupDesc const_load(const GroupDesc *p) {
+    struct Words {
+        uint32_t w[sizeof(GroupDesc) / 4];
+    } v;
+    static_assert(sizeof(GroupDesc) % 4 == 0, "descriptor of whole words");
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(GroupDesc) / 4); ++i) v.w[i] = q[i];
+    return __builtin_bit_cast(GroupDesc, v);
+}
+
+template <class Tile>
+__device__ __forceinline__ void walk_tiles(const GroupArgs &g, Tile &&tile) {
+    GroupWalk w(g);
+    if (w.t >= w.end) return;
+    int gnext = const_load(g.tile_group + w.t);
+    GroupDesc d = const_load(g.descs + gnext);
+    if (w.t + w.stride < w.end) gnext = const_load(g.tile_group + w.t + w.stride);
+    for (; w.t < w.end; w.t += w.stride) {
+        const int64_t t2 = w.t + 2 * w.stride;
+        const int gafter = t2 < w.end ? const_load(g.tile_group + t2) : gnext;
+        const GroupDesc dn = const_load(g.descs + gnext);
+        __syncthreads();  // the previous tile's LDS reads are done
+        tile(d, (int)(w.t - d.tile_start));
+        d = dn;
+        gnext = gafter;
+    }
+}
+
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
 __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
     using L = F32Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) float As[STAGES * L::A];
     __shared__ __attribute__((aligned(16))) float Bs[STAGES * L::B];
-    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
-        const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int local = (int)(w.t - d.tile_start);  // a product's tiles fit 32 bits
+    walk_tiles(g, [&](const GroupDesc &d, int local) {
         const int tm = local / d.tiles_n, tn = local % d.tiles_n;
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        __syncthreads();  // the previous tile's LDS reads are done
         mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
-    }
+    });
 }
 
 template <int BM, int BN, int BK, int WM, int WN, int STAGES>
@@ -750,14 +788,11 @@ __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
     using L = Bf16Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[STAGES * L::B];
-    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
-        const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int local = (int)(w.t - d.tile_start);  // a product's tiles fit 32 bits
+    walk_tiles(g, [&](const GroupDesc &d, int local) {
         const int tm = local / d.tiles_n, tn = local % d.tiles_n;
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        __syncthreads();
         mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
-    }
+    });
 }
 
 // Mixed grouped kernels: each product's tiles run the program kMixedTile[prog]
@@ -801,36 +836,30 @@ template <int STAGES>
 __device__ __forceinline__ void grouped_mixed_f32(const GroupArgs &g) {
     static_assert(kMixedPrograms == 4, "one case per program");
     __shared__ __attribute__((aligned(16))) float lds[MixedLds<STAGES>::f32];
-    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
-        const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int local = (int)(w.t - d.tile_start);
+    walk_tiles(g, [&](const GroupDesc &d, int local) {
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        __syncthreads();  // the previous tile's LDS reads are done
         switch (d.prog) {
         case 0: mixed_f32_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
         case 1: mixed_f32_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
         case 2: mixed_f32_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
         default: mixed_f32_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
         }
-    }
+    });
 }
 
 template <int STAGES>
 __device__ __forceinline__ void grouped_mixed_bf16(const GroupArgs &g) {
     static_assert(kMixedPrograms == 4, "one case per program");
     __shared__ __attribute__((aligned(16))) unsigned short lds[MixedLds<STAGES>::bf16];
-    for (GroupWalk w(g); w.t < w.end; w.t += w.stride) {
-        const GroupDesc &d = g.descs[g.tile_group[w.t]];
-        const int local = (int)(w.t - d.tile_start);
+    walk_tiles(g, [&](const GroupDesc &d, int local) {
         const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        __syncthreads();
         switch (d.prog) {
         case 0: mixed_bf16_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
         case 1: mixed_bf16_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
         case 2: mixed_bf16_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
         default: mixed_bf16_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
         }
-    }
+    });
 }
 
 }  // namespace pkk
