@@ -116,4 +116,9 @@ def test_counter_means_and_ratios(tmp_path):
     assert list(res) == ["pk_a"] and res["pk_a"]["dispatches"] == 2
     m = res["pk_a"]["mean"]
     assert m["SQ_VALU_MFMA_BUSY_CYCLES"] == 2 * (35.0 + 36.0) / 2 and m["GRBM_GUI_ACTIVE"] == 100.0
-    assert res["pk_a"]["ratios"] == {"mfma_busy_per_active": 0.71, "lds_conflict_per_active": 0.25}
+    # GRBM_GUI_ACTIVE is summed over the 8 XCDs: 100 / 8 cycles, 1024 SIMDs, 256 CUs
+    assert res["pk_a"]["ratios"] == {"mfma_util": round(71.0 / (12.5 * 1024), 4),
+                                     "lds_active": round(40.0 / (12.5 * 256), 4),
+                                     "lds_conflict_per_active": 0.25}
+    res = counters.summarize([str(tmp_path)], durations={"pk_a": 10.0})
+    assert res["pk_a"]["ratios"]["clock_ghz"] == 1.25
