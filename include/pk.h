@@ -475,12 +475,12 @@ int pk_instance_count(void);
 const char *pk_instance_name(int i);
 
 /* ------------------------------------------------------------------ cost model */
-/* The learned cost model: a 12-64-64-1 ReLU network predicting ln(seconds)
+/* The learned cost model: a 13-64-64-1 ReLU network predicting ln(seconds)
  * of a candidate launch from PK_NFEATURES features, trained on the device by
  * the library's own kernels (forward, backward, Adam) on timings from
  * pk_measure.  Not in the paper: it stands in for the auto-tuning the paper
  * leaves open for the program parameters (Section 1). */
-#define PK_NFEATURES 12
+#define PK_NFEATURES 13
 typedef struct pk_costmodel pk_costmodel; /* opaque */
 
 /* Features of candidate *p for C(MxN) = A(MxK) B(KxN) on the bound machine:
@@ -489,8 +489,10 @@ typedef struct pk_costmodel pk_costmodel; /* opaque */
  * padding efficiency, wave quantisation efficiency (workgroups: tiles times
  * the shares of K), `wide` (1 when the operands' rows are aligned for the
  * MFMA programs' 16-byte loads, 0 when they run as their element-load twins;
- * see pk_matmul), and ln of the shares of K (p->ks; 0 unsplit).  out: PK_NFEATURES
- * floats.  Errors as pk_launch_shape. */
+ * see pk_matmul), ln of the shares of K (p->ks; 0 unsplit), and ln of the
+ * analytic estimate of the launch's seconds (pk_estimate with the same
+ * arguments): the network learns a correction to the estimate the CASE
+ * policy ranks by.  out: PK_NFEATURES floats.  Errors as pk_launch_shape. */
 int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t M, int64_t N, int64_t K, int wide,
                 float *out);
 
@@ -510,9 +512,9 @@ int pk_costmodel_train(const pk_table *tbl, const float *X, const float *seconds
 int pk_costmodel_predict(const pk_costmodel *cm, int device, const float *X, int64_t n, float *log_seconds);
 
 /* The network's raw forward/backward on the device: mean squared error of
- * the network with parameters `params` (host, 5057 floats in the order W1
- * (64x11), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x 11, host) and
- * targets t (host); writes the gradient (5057 floats) and the loss.  Used to
+ * the network with parameters `params` (host, 5121 floats in the order W1
+ * (64 x PK_NFEATURES), b1, W2 (64x64), b2, W3 (1x64), b3) on rows X (n x PK_NFEATURES, host) and
+ * targets t (host); writes the gradient (5121 floats) and the loss.  Used to
  * check the kernels against a float64 reference. */
 int pk_costmodel_grad(int device, const float *params, const float *X, const float *t, int64_t n, float *grad,
                       float *loss);
@@ -521,7 +523,7 @@ int pk_costmodel_grad(int device, const float *params, const float *X, const flo
  * place; step >= 1 is the step number used for bias correction). */
 int pk_costmodel_adam_step(int device, float *params, const float *grad, float *m, float *v, int64_t step, float lr);
 
-/* Parameter export (*n = 5057; out may be NULL to query), text save/load
+/* Parameter export (*n = 5121; out may be NULL to query), text save/load
  * (the file carries the standardisation, the machine and the element type
  * it was trained on; a file without a dtype line is float32), release, and
  * the machine fingerprint string. */

@@ -14,8 +14,9 @@ enumeration over a grid of machines and the whole program-parameter domain:
 * 2-D VALU family (Fig. 4's kernel with outputs per work-item along M too):
   program parameters bx, by, s (outputs per work-item along N), sy (along
   M), bk (the LDS tiles' K extent, free of by); programs {} and {gran} (one
-  output per work-item, s = sy = 1).  LDS bytes: 4 * (by * sy' * (bk + 1) +
-  bk * bx * s'); threads: bx * by.
+  output per work-item, s = sy = 1).  LDS bytes: 4 * (by * sy' * (bk + 4) +
+  bk * bx * s') (A rows padded to bk + 4 elements, a 16-byte multiple);
+  threads: bx * by.
 * MFMA family: program parameters bm, bn, bk, wm, wn; programs {} (two LDS
   stages) and {single} (one).  One stage holds, in float32, an A tile bm x
   (bk + 4) and a B tile bk x (bn + 4); in bfloat16 an A tile bm x (bk + 8) and
@@ -38,7 +39,9 @@ enumeration over a grid of machines and the whole program-parameter domain:
   of a and of b and the leading coefficient: 4 * (2 * s' * B + 1) bytes;
   threads B; 32-bit residues only (stored under the int32 dtype).
 * An MFMA program also exists as an element-load twin (rows not aligned for
-  16-byte loads); the program's registers are the larger of the two.
+  16-byte loads) and, up to 512 work-items, as a split form running a share
+  of K; the program's registers are the largest of its kernels' (any of them
+  may run it).
 * Registers of a workgroup: each lane of a wavefront allocates its VGPRs
   rounded up to 4 plus its AGPRs, rounded up to 8 (gfx950's unified register
   file); a workgroup occupies ceil(threads / 64) wavefronts of 64 lanes.  The
@@ -64,6 +67,7 @@ VALU, MFMA, TRANSPOSE, MADD, JACOBI, POLYDIV, VALU2 = 0, 1, 2, 3, 4, 5, 6
 GRAN, NOLDS = 1, 2          # VALU strategy bits
 SINGLE = 1                  # MFMA strategy bit
 ELEMENT = 4                 # MFMA: the twin instance reading rows element by element
+SPLIT = 16                  # MFMA: the form running a share of K (products split along K)
 
 VALU_VARIANTS = (0, GRAN, GRAN | NOLDS, NOLDS)
 MFMA_VARIANTS = (0, SINGLE)
@@ -92,7 +96,7 @@ def valu_lds(variant: int, bx: int, by: int, s: int) -> int:
 
 def valu2_lds(variant: int, bx: int, by: int, s: int, sy: int, bk: int) -> int:
     outs, rows = (1, 1) if variant & GRAN else (s, sy)
-    return 4 * (by * rows * (bk + 1) + bk * bx * outs)
+    return 4 * (by * rows * (bk + 4) + bk * bx * outs)
 
 
 def transpose_lds(variant: int, bx: int, by: int, s: int) -> int:
@@ -163,10 +167,9 @@ class InstanceData:
             e = self.by_key.get((family, dt, kernel, bx, by, outs))
         else:
             e = self.by_key.get((MFMA, dtype, variant & SINGLE) + tuple(point))
-            twin = self.by_key.get((MFMA, dtype, (variant & SINGLE) | ELEMENT) + tuple(point))
-            if e is not None and twin is not None and "vgpr" in e:
-                return max(regs_per_block(e["vgpr"], e["agpr"], e["threads"]),
-                           regs_per_block(twin["vgpr"], twin["agpr"], twin["threads"]))
+            forms = [self.by_key.get((MFMA, dtype, (variant & SINGLE) | f) + tuple(point)) for f in (ELEMENT, SPLIT)]
+            if e is not None and "vgpr" in e:
+                return max(regs_per_block(k["vgpr"], k["agpr"], k["threads"]) for k in [e] + forms if k is not None)
         if e is None or "vgpr" not in e:
             return None
         return regs_per_block(e["vgpr"], e["agpr"], e["threads"])
@@ -276,8 +279,8 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
 
         def lds_poly(applied):
             if "gran" in applied:
-                return co.parse_poly("4*(by*(bk+1) + bk*bx)")
-            return co.parse_poly("4*(by*sy*(bk+1) + bk*bx*s)")
+                return co.parse_poly("4*(by*(bk+4) + bk*bx)")
+            return co.parse_poly("4*(by*sy*(bk+4) + bk*bx*s)")
 
         def bits(applied):
             return GRAN if "gran" in applied else 0

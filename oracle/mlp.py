@@ -5,21 +5,21 @@ step the paper leaves open (program parameters "can be deduced, for instance,
 by auto-tuning", Section 1).  This module is the plain definition of what the
 HIP kernels compute, in float64 and numpy:
 
-* network: x (IN = 12 features) -> h1 = relu(W1 x + b1) (64) -> h2 =
-  relu(W2 h1 + b2) (64) -> y = W3 h2 + b3 (1); 5057 parameters;
+* network: x (IN = 13 features) -> h1 = relu(W1 x + b1) (64) -> h2 =
+  relu(W2 h1 + b2) (64) -> y = W3 h2 + b3 (1); 5121 parameters;
 * loss: mean squared error L = (1/n) sum_r (y_r - t_r)^2;
 * gradients: the chain rule written out layer by layer (relu'(z) = [z > 0]);
 * Adam (Kingma and Ba, 2015): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
   mhat = m / (1-b1^t), vhat = v / (1-b2^t), p <- p - lr mhat / (sqrt(vhat) + eps).
 
-Parameter order (also the flat layout): W1 (64x12, row-major), b1 (64),
+Parameter order (also the flat layout): W1 (64x13, row-major), b1 (64),
 W2 (64x64), b2 (64), W3 (1x64), b3 (1).
 """
 from __future__ import annotations
 
 import numpy as np
 
-IN, H1, H2, OUT = 12, 64, 64, 1
+IN, H1, H2, OUT = 13, 64, 64, 1
 SHAPES = (("W1", (H1, IN)), ("b1", (H1,)), ("W2", (H2, H1)), ("b2", (H2,)),
           ("W3", (OUT, H2)), ("b3", (OUT,)))
 NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)

@@ -81,7 +81,7 @@ def valu_lds(bx, by, s, nolds):
 
 
 def valu2_lds(bx, by, sx, sy, bk):
-    return 4 * (by * sy * (bk + 1) + bk * bx * sx)
+    return 4 * (by * sy * (bk + 4) + bk * bx * sx)
 
 
 def mfma_reg_cap(dt, threads, stages, kind, bm=0, bn=0):

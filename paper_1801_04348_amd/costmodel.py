@@ -5,10 +5,13 @@
 
 train: one row per (shape, candidate) of the stores (written by tune.py on
 this device): the library's features of the candidate (pk_features) and its
-measured seconds; the network is trained on the device by the library
-(pk_costmodel_train) and saved with its standardisation, the machine and the
-element type it was trained on (one model per type; the stores must not mix
-types).
+measured seconds; rows within --near (1.3) times their shape's fastest
+candidate are repeated --copies (8) times in all, so the squared error
+weighs most where the choice is made (a plain mean over every candidate is
+dominated by programs that never win); the network is trained on the device
+by the library (pk_costmodel_train) and saved with its standardisation, the
+machine and the element type it was trained on (one model per type; the
+stores must not mix types).
 
 eval: for every shape of a held-out store, the LEARNED choice as pk_select
 makes it -- the candidate with the least predicted time, except that when the
@@ -81,6 +84,9 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--near", type=float, default=1.3,
+                    help="train: rows within this factor of their shape's fastest candidate are repeated")
+    ap.add_argument("--copies", type=int, default=8, help="train: copies of each such row (1: no repetition)")
     args = ap.parse_args()
 
     import numpy as np
@@ -101,8 +107,9 @@ def main():
 
     if args.cmd == "train":
         Xs, ts = zip(*(feature_rows(pk, tbl, r) for r in recs))
-        X = np.concatenate(Xs).astype(np.float32)
-        t = np.concatenate(ts)
+        near = [np.repeat(np.arange(len(t_)), np.where(t_ <= args.near * t_.min(), args.copies, 1)) for t_ in ts]
+        X = np.concatenate([x[i] for x, i in zip(Xs, near)]).astype(np.float32)
+        t = np.concatenate([t_[i] for t_, i in zip(ts, near)])
         import time
         t0 = time.perf_counter()
         cm, loss = pk.pk_costmodel_train(tbl, X, t, epochs=args.epochs, lr=args.lr, seed=args.seed)
@@ -111,7 +118,8 @@ def main():
         pred = cm.predict(X)
         rmse = float(np.sqrt(np.mean((pred - np.log(t)) ** 2)))
         cm.save(args.out)
-        print(json.dumps({"dtype": dtype, "rows": int(X.shape[0]), "shapes": len(recs), "epochs": args.epochs,
+        print(json.dumps({"dtype": dtype, "rows": int(X.shape[0]), "distinct_rows": int(sum(len(t_) for t_ in ts)),
+                          "near": args.near, "copies": args.copies, "shapes": len(recs), "epochs": args.epochs,
                           "lr": args.lr,
                           "loss_standardised": loss, "rmse_ln_seconds": rmse, "train_seconds": round(train_s, 3),
                           "ms_per_epoch": round(train_s / args.epochs * 1e3, 4), "model": args.out}), flush=True)

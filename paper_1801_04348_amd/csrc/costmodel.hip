@@ -1,10 +1,10 @@
-// Learned cost model: a 12-64-64-1 ReLU network that predicts the logarithm
+// Learned cost model: a 13-64-64-1 ReLU network that predicts the logarithm
 // of a candidate's launch time from features of (candidate, M, N, K), trained
 // on the device by the kernels below on timings the exhaustive tuner records.
 // It replaces the analytic score when selecting among the case table's
 // feasible (leaf, E) pairs, with measurement as its fallback.
 //
-// Network (parameters flat, in this order): W1 (64 x 12, row-major), b1 (64),
+// Network (parameters flat, in this order): W1 (64 x 13, row-major), b1 (64),
 // W2 (64 x 64), b2 (64), W3 (1 x 64), b3 (1):
 //   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3.
 // Loss: mean squared error over the n rows.  Optimiser: Adam.
@@ -263,8 +263,10 @@ std::string machine_fingerprint(const pk_machine &m) {
 //   10   1 where the operands' rows allow the MFMA programs' 16-byte loads
 //        (else the element-load twin runs), 0 otherwise
 //   11   ln(shares of K): 0 for a product not split along K
-void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, int ks,
-              float *f) {
+//   12   ln of the analytic estimate of the launch's seconds (estimate_seconds,
+//        the CASE policy's ranking)
+void features(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K, bool wide,
+              int ks, float *f) {
     const int wave = m.wave > 0 ? m.wave : 64;
     const int64_t tm = (M + e.tile_m - 1) / e.tile_m, tn = (N + e.tile_n - 1) / e.tile_n;
     ks = ks > 1 ? ks : 1;
@@ -286,6 +288,7 @@ void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, i
     f[9] = (float)((double)tiles / ((double)rounds * slots));
     f[10] = wide ? 1.0f : 0.0f;
     f[11] = (float)std::log((double)ks);
+    f[12] = (float)std::log(estimate_seconds(m, e, dtype, M, N, K, wide, ks));
 }
 
 // ln(seconds) predictions for rows of raw features, on `device`
@@ -322,7 +325,7 @@ int pk_features(const pk_table *tbl, const pk_params *p, pk_dtype dtype, int64_t
     const KernelEntry *e = nullptr;
     int rc = resolve(tbl, p, (int)dtype, &q, &e);
     if (rc != PK_OK) return rc;
-    features(tbl->machine, *e, M, N, K, wide != 0, q.ks, out);
+    features(tbl->machine, *e, (int)dtype, M, N, K, wide != 0, q.ks, out);
     return PK_OK;
 }
 

@@ -208,9 +208,9 @@ Family matmul_family(int family, int dtype) {
                     for (int zy : kValu2S)
                         for (int k : kValu2Bk) f.points.push_back({x, y, z, zy, k});
             }
-        // LDS bytes: A tile (by sy) x (bk + 1) and B tile bk x (bx s)
-        const Poly lds_full = P(es) * (S(by) * S(sy) * (S(bk) + P(1)) + S(bk) * S(bx) * S(s));
-        const Poly lds_g1 = P(es) * (S(by) * (S(bk) + P(1)) + S(bk) * S(bx));
+        // LDS bytes: A tile (by sy) x (bk + 4) and B tile bk x (bx s)
+        const Poly lds_full = P(es) * (S(by) * S(sy) * (S(bk) + P(4)) + S(bk) * S(bx) * S(s));
+        const Poly lds_g1 = P(es) * (S(by) * (S(bk) + P(4)) + S(bk) * S(bx));
         CounterDef rz{"r_Z", false, m.Z, nullptr};
         rz.value = [=](uint32_t ap) { return (ap & PK_VALU_GRAN) ? lds_g1 : lds_full; };
         CounterDef rv{"r_V", false, m.V, nullptr};

@@ -292,20 +292,29 @@ int build_from(const pk_table *tbl, int dtype, const GroupedOperands &o, const s
     for (const KernelEntry *e : order) {
         std::vector<int> gs = by_entry[e];
         std::vector<int64_t> tiles(o.G, 0);
+        // estimated cost of one tile of each product: its K steps' work (the
+        // estimate of a one-tile product, the same figure for every product
+        // of one program and K) plus one step more for what every tile pays
+        // once -- the first step's loads, which nothing overlaps, and the
+        // stores of its results.  Without that term tiles of one or two K
+        // steps count as nearly free and the XCD that gets them runs last.
+        std::vector<double> tile_cost(o.G, 0.0);
         for (int g : gs) {
             const Assign &a = as[g];
             tiles[g] = ((o.M[g] + a.tile_m - 1) / a.tile_m) * ((o.N[g] + a.tile_n - 1) / a.tile_n);
+            const KernelEntry pe = (a.entry->variant & PK_MFMA_MIXED) ? as_program(*a.entry, a.prog) : *a.entry;
+            const int64_t bk = pe.bk > 0 ? pe.bk : 1;
+            const double ks = (double)((std::max<int64_t>(o.K[g], 1) + bk - 1) / bk);
+            tile_cost[g] = tile_work_seconds(tbl->machine, pe, dtype, pe.tile_m, pe.tile_n, o.K[g]) * (ks + 1.0) / ks;
         }
         // most expensive tiles first
-        std::stable_sort(gs.begin(), gs.end(), [&](int x, int y) {
-            return as[x].cost / (double)tiles[x] > as[y].cost / (double)tiles[y];
-        });
+        std::stable_sort(gs.begin(), gs.end(), [&](int x, int y) { return tile_cost[x] > tile_cost[y]; });
         GroupedLaunch L;
         L.entry = e;
         L.first_desc = (int64_t)lay.descs.size();
         L.first_tile = (int64_t)lay.tmap.size();
         double total = 0.0;
-        for (int g : gs) total += as[g].cost;
+        for (int g : gs) total += tile_cost[g] * (double)tiles[g];
         const bool cost_known = total > 0.0;
         if (!cost_known) {  // no estimate: cut by tile count
             total = 0.0;
@@ -333,7 +342,7 @@ int build_from(const pk_table *tbl, int dtype, const GroupedOperands &o, const s
             d.tiles_n = (int32_t)((o.N[g] + a.tile_n - 1) / a.tile_n);
             d.prog = a.prog;
             const int32_t local = (int32_t)(lay.descs.size() - L.first_desc);
-            const double per_tile = cost_known ? a.cost / (double)tiles[g] : 1.0;
+            const double per_tile = cost_known ? tile_cost[g] : 1.0;
             for (int64_t i = 0; i < tiles[g]; ++i) {
                 // cut before this tile where the cost so far reaches the
                 // next bin's share

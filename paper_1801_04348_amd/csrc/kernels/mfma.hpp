@@ -15,7 +15,13 @@
 // STAGES = 2 double-buffers the tiles (one barrier per K step: the next tile is
 // fetched from global memory into registers while the current one is
 // consumed); STAGES = 1 keeps one buffer and two barriers per step, as in the
-// paper's kernel.  LDS bytes = STAGES * (A tile + B tile).
+// paper's kernel, with the next step's loads in flight in registers while the
+// current step multiplies out of LDS.  LDS bytes = STAGES * (A tile + B tile).
+// Left to itself, the compiler's scheduler sinks those loads to the end of the
+// step (shortening their registers' lives) and the step then waits out a whole
+// global-memory latency; a scheduling barrier keeps them ahead of the products
+// in programs whose wavefronts hold at least a 64 x 64 tile (few wavefronts per
+// SIMD to hide the latency otherwise) and in every single-stage program.
 //
 // The order in which k enters each 32x32 block's sum is permuted: lanes 0-31
 // consume k in the first half of the LDS tile and lanes 32-63 the second half,
@@ -111,6 +117,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
     static_assert(TM >= 1 && TN >= 1 && WTM % 32 == 0 && WTN % 32 == 0, "wave tile must be 32x32 blocks");
     static_assert(A4 >= 1 && B4 >= 1 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tile loads");
     static_assert(BK % 8 == 0, "BK");
+    constexpr bool PIN = TM * TN >= 4;  // two stages: the next step's loads ahead of the products
 
 
     // the operands from this workgroup's first K step on: its steps run from
@@ -312,6 +319,7 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         for (; kt + 1 < KF; ++kt) {
             const int cur = kt & 1;
             gload_fast((kt + 1) * BK);
+            if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
@@ -319,24 +327,35 @@ __device__ __forceinline__ void mfma_f32_tile(const MmArgs &a, const int row0, c
         for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
+            if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
             if (!idle) compute(cur);
             if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
+        // one LDS buffer: step kt + 1's loads are in flight (in registers)
+        // while step kt multiplies out of LDS
+        if (KT > 0) {
+            if (KF > 0)
+                gload_fast(0);
+            else
+                gload(0);
+        }
         int kt = 0;
-        for (; kt < KF; ++kt) {
-            gload_fast(kt * BK);
-            __syncthreads();
+        for (; kt + 1 < KF; ++kt) {
+            __syncthreads();  // the previous step's LDS reads are done
             sstore(0);
             __syncthreads();
+            gload_fast((kt + 1) * BK);
+            __builtin_amdgcn_sched_barrier(0);
             compute(0);
         }
         for (; kt < KT; ++kt) {
-            gload(kt * BK);
             __syncthreads();
             sstore(0);
             __syncthreads();
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            __builtin_amdgcn_sched_barrier(0);
             if (!idle) compute(0);
         }
     }
@@ -401,6 +420,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
     static_assert(A8 >= 1 && B8 >= 1 && (BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tile loads");
     static_assert(BK % 32 == 0 && BN % 8 == 0, "BK, BN");
     static_assert((LDB_S * 2) % 256 == 64 || (LDB_S * 2) % 256 == 192, "B rows one quarter of the banks apart");
+    constexpr bool PIN = true;  // two stages: the next step's loads ahead of the products
 
     // from this workgroup's first K step on, as in the float32 tile
     const gptr<unsigned short> __restrict__ A = (gptr<unsigned short>)a.A + kt0 * BK;
@@ -599,6 +619,7 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         for (; kt + 1 < KF; ++kt) {
             const int cur = kt & 1;
             gload_fast((kt + 1) * BK);
+            if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
             compute(cur);
             sstore(cur ^ 1);
             __syncthreads();
@@ -606,24 +627,35 @@ __device__ __forceinline__ void mfma_bf16_tile(const MmArgs &a, const int row0, 
         for (; kt < KT; ++kt) {
             const int cur = kt & 1;
             if (kt + 1 < KT) gload((kt + 1) * BK);
+            if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
             if (!idle) compute(cur);
             if (kt + 1 < KT) sstore(cur ^ 1);
             __syncthreads();
         }
     } else {
+        // one LDS buffer: step kt + 1's loads are in flight (in registers)
+        // while step kt multiplies out of LDS
+        if (KT > 0) {
+            if (KF > 0)
+                gload_fast(0);
+            else
+                gload(0);
+        }
         int kt = 0;
-        for (; kt < KF; ++kt) {
-            gload_fast(kt * BK);
-            __syncthreads();
+        for (; kt + 1 < KF; ++kt) {
+            __syncthreads();  // the previous step's LDS reads are done
             sstore(0);
             __syncthreads();
+            gload_fast((kt + 1) * BK);
+            __builtin_amdgcn_sched_barrier(0);
             compute(0);
         }
         for (; kt < KT; ++kt) {
-            gload(kt * BK);
             __syncthreads();
             sstore(0);
             __syncthreads();
+            if (kt + 1 < KT) gload((kt + 1) * BK);
+            __builtin_amdgcn_sched_barrier(0);
             if (!idle) compute(0);
         }
     }

@@ -151,21 +151,29 @@ __device__ __forceinline__ void valu_tiled(const MmArgs &a) {
 // valu_tiled2 (the 2-D micro-tile program, Fig. 4's kernel with outputs per
 // work-item along M as well): a workgroup of BX x BY work-items owns a tile
 // of BY * SY rows and BX * SX columns; work-item (ty, tx) computes the outputs
-// at rows row0 + ty + v * BY (v < SY) and columns col0 + tx + w * BX (w < SX),
-// so a store of the workgroup still writes consecutive columns per row.  The
-// LDS tiles are the A tile (BY * SY) x BK, rows padded by one element, and
-// the B tile BK x (BX * SX), with a K extent BK of its own.  Per k a
-// work-item reads SY + SX LDS words for SY * SX multiply-adds (the paper's
-// program, SY = 1, reads 1 + S for S), which is what lifts the LDS bound.
-// Each output sums k in ascending order, as the one-row program does.
+// at rows row0 + ty + v * BY (v < SY) and the SX consecutive columns
+// col0 + tx * SX + w (w < SX), so a workgroup's store of one row is still one
+// contiguous run.  The LDS tiles are the A tile (BY * SY) x BK, rows padded to
+// BK + 4 elements (16-byte aligned rows; the rows one wavefront reads start
+// four banks apart), and the B tile BK x (BX * SX), with a K extent BK of its
+// own.  Per four k a work-item reads SY 16-byte words of A (four k of one row;
+// shared by the BX work-items of that row) and four SX-element words of B
+// (contiguous across the lanes), for 4 * SY * SX multiply-adds: the paper's
+// program (SY = 1, one element per read) reads 1 + S elements per S.  Each
+// output sums k in ascending order, as the one-row program does.
 template <typename T, int BX, int BY, int SX, int SY, int BK>
 __device__ __forceinline__ void valu_tiled2(const MmArgs &a) {
     using U = typename Acc<T>::type;
     constexpr int NT = BX * BY;
     constexpr int TM = BY * SY;
     constexpr int TN = BX * SX;
-    __shared__ T As[TM][BK + 1];
-    __shared__ T Bs[BK][TN];
+    constexpr int LDA = BK + 4;
+    static_assert(BK % 4 == 0, "K tile of whole 16-byte words");
+    static_assert(SX == 1 || SX == 2 || SX == 4, "B words of 1, 2 or 4 elements");
+    __shared__ __attribute__((aligned(16))) T As[TM][LDA];
+    __shared__ __attribute__((aligned(16))) T Bs[BK][TN];
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    typedef T tsx __attribute__((ext_vector_type(SX == 1 ? 2 : SX)));  // SX == 1 reads one element
 
     const T *__restrict__ A = static_cast<const T *>(a.A);
     const T *__restrict__ B = static_cast<const T *>(a.B);
@@ -185,7 +193,7 @@ __device__ __forceinline__ void valu_tiled2(const MmArgs &a) {
         for (int v = 0; v < SY; ++v)
 #pragma unroll
             for (int w = 0; w < SX; ++w) {
-                const int row = row0 + ty + v * BY, col = col0 + tx + w * BX;
+                const int row = row0 + ty + v * BY, col = col0 + tx * SX + w;
                 acc[v][w] = (a.accumulate && row < M && col < N) ? Acc<T>::from(C[(int64_t)row * a.ldc + col]) : U(0);
             }
         const bool inside = row0 + TM <= M && col0 + TN <= N;
@@ -238,16 +246,27 @@ __device__ __forceinline__ void valu_tiled2(const MmArgs &a) {
             }
             __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < BK; ++kk) {
-                U av[SY], bv[SX];
+            for (int kk = 0; kk < BK; kk += 4) {
+                t4 av[SY];
+                U bv[4][SX];
 #pragma unroll
-                for (int v = 0; v < SY; ++v) av[v] = (U)As[ty + v * BY][kk];
+                for (int v = 0; v < SY; ++v) av[v] = *reinterpret_cast<const t4 *>(&As[ty + v * BY][kk]);
 #pragma unroll
-                for (int w = 0; w < SX; ++w) bv[w] = (U)Bs[kk][tx + w * BX];
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (SX == 1) {
+                        bv[q][0] = (U)Bs[kk + q][tx];
+                    } else {
+                        const tsx b = *reinterpret_cast<const tsx *>(&Bs[kk + q][tx * SX]);
 #pragma unroll
-                for (int v = 0; v < SY; ++v)
+                        for (int w = 0; w < SX; ++w) bv[q][w] = (U)b[w];
+                    }
+                }
 #pragma unroll
-                    for (int w = 0; w < SX; ++w) acc[v][w] = Acc<T>::mad(acc[v][w], av[v], bv[w]);
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int v = 0; v < SY; ++v)
+#pragma unroll
+                        for (int w = 0; w < SX; ++w) acc[v][w] = Acc<T>::mad(acc[v][w], (U)av[v][q], bv[q][w]);
             }
             __syncthreads();
         }
@@ -255,7 +274,7 @@ __device__ __forceinline__ void valu_tiled2(const MmArgs &a) {
         for (int v = 0; v < SY; ++v)
 #pragma unroll
             for (int w = 0; w < SX; ++w) {
-                const int row = row0 + ty + v * BY, col = col0 + tx + w * BX;
+                const int row = row0 + ty + v * BY, col = col0 + tx * SX + w;
                 if (row < M && col < N) C[(int64_t)row * a.ldc + col] = Acc<T>::to(acc[v][w]);
             }
     }

@@ -354,7 +354,7 @@ int select_params(const pk_table *tbl, int dtype, int64_t M, int64_t N, int64_t 
         std::vector<float> X(cands.size() * PK_NFEATURES), pred(cands.size());
         const bool wide = !A || wide_rows(dtype, A, lda, B, ldb);
         for (size_t i = 0; i < cands.size(); ++i)
-            features(tbl->machine, *cands[i].entry, M, N, K, wide, cands[i].ks, &X[i * PK_NFEATURES]);
+            features(tbl->machine, *cands[i].entry, dtype, M, N, K, wide, cands[i].ks, &X[i * PK_NFEATURES]);
         costmodel_predict(*model, tbl->device, X.data(), (int64_t)cands.size(), pred.data());
         std::vector<int> order(cands.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;

@@ -86,8 +86,8 @@ int resolve(const pk_table *tbl, const pk_params *pin, int dtype, pk_params *pou
 
 // cost model (costmodel.hip)
 std::string machine_fingerprint(const pk_machine &m);
-void features(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N, int64_t K, bool wide, int ks,
-              float *f);
+void features(const pk_machine &m, const KernelEntry &e, int dtype, int64_t M, int64_t N, int64_t K, bool wide,
+              int ks, float *f);
 void costmodel_predict(const pk_costmodel &cm, int device, const float *X, int64_t n, float *out);
 
 }  // namespace pk

@@ -463,7 +463,7 @@ def pk_matmul(tbl: Table, p, dtype, A, B, C, accumulate: bool = False, stream=No
 
 
 # ---------------------------------------------------------------------- cost model
-PK_NFEATURES = 12
+PK_NFEATURES = 13
 
 
 def _fbuf(a):

@@ -102,16 +102,19 @@ def test_features_by_hand():
     rounds = math.ceil(tiles / slots)
     want = [math.log(M), math.log(N), math.log(K), math.log(128), math.log(128), math.log(128 * 128 / 256),
             inst["lds_bytes"] / 65536, min(1.0, occ * 4 / (m.max_threads_cu / 64)),
-            M * N / (math.ceil(M / 128) * 128 * math.ceil(N / 128) * 128), tiles / (rounds * slots), 1.0, 0.0]
+            M * N / (math.ceil(M / 128) * 128 * math.ceil(N / 128) * 128), tiles / (rounds * slots), 1.0, 0.0,
+            math.log(pk.pk_estimate(t, p, "f32", M, N, K))]
     assert np.allclose(f, want, rtol=1e-6, atol=1e-7), (f, want)
     f0 = pk.pk_features(t, p, "f32", M, N, K, wide=False)
     assert f0[10] == 0.0 and np.array_equal(f0[:10], f[:10])
-    # split along K in 4: four workgroups per tile, ln 4 as the last feature
+    assert np.isclose(f0[12], math.log(pk.pk_estimate(t, p, "f32", M, N, K, wide=False)), rtol=1e-6)
+    # split along K in 4: four workgroups per tile, ln 4 as feature 11
     p.ks = 4
     f4 = pk.pk_features(t, p, "f32", M, N, K)
     rounds4 = math.ceil(4 * tiles / slots)
     assert np.isclose(f4[9], 4 * tiles / (rounds4 * slots)) and np.isclose(f4[11], math.log(4))
-    assert np.array_equal(np.delete(f4, [9, 11]), np.delete(f, [9, 11]))
+    assert np.isclose(f4[12], math.log(pk.pk_estimate(t, p, "f32", M, N, K)), rtol=1e-6) and f4[12] != f[12]
+    assert np.array_equal(np.delete(f4, [9, 11, 12]), np.delete(f, [9, 11, 12]))
     assert pk.packed_rows_wide("f32", 3000, 512) and not pk.packed_rows_wide("f32", 3000, 513)
     assert pk.packed_rows_wide("bf16", 3000, 512) and not pk.packed_rows_wide("bf16", 3001, 512)
 

@@ -11,7 +11,7 @@ def _data(n, seed):
 
 
 def test_parameter_count():
-    assert mlp.NPARAM == 64 * 12 + 64 + 64 * 64 + 64 + 64 + 1 == 5057
+    assert mlp.NPARAM == 64 * 13 + 64 + 64 * 64 + 64 + 64 + 1 == 5121
 
 
 def test_gradient_matches_central_differences():
