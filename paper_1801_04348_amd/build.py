@@ -241,27 +241,34 @@ def instances():
             for stages in (2, 1):
                 if dt == BF16 and bm * bn >= 128 * 128 and stages == 2:
                     continue  # would spill at 256 registers a lane (its loads at chosen addresses hold more)
-                name = "pk_grouped_%s_%dx%dx%d_w%dx%d_st%d" % (DT_NAME[dt], bm, bn, bk, wm, wn, stages)
-                body = "pkk::%s<%d, %d, %d, %d, %d, %d>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages)
-                entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE),
-                             dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
-                             lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
-                             attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "grouped"))
-                out.append(("grouped_%s" % DT_NAME[dt], name, body, entry))
+                # the wide kernel (rows aligned for 16-byte loads) and its
+                # element-load twin, for the products whose rows are not
+                for wide in (True, False):
+                    name = "pk_grouped_%s_%dx%dx%d_w%dx%d_st%d%s" % (DT_NAME[dt], bm, bn, bk, wm, wn, stages,
+                                                                   "" if wide else "_el")
+                    body = "pkk::%s<%d, %d, %d, %d, %d, %d, %s>(g);" % (gfn[dt], bm, bn, bk, wm, wn, stages,
+                                                                       "true" if wide else "false")
+                    entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | (0 if stages == 2 else MFMA_SINGLE) |
+                                 (0 if wide else MFMA_ELEMENT), dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn,
+                                 wm=wm, wn=wn, threads=64 * wm * wn, lds=mfma_lds(dt, bm, bn, bk, stages), tile_m=bm,
+                                 tile_n=bn, args="pkk::GroupArgs g",
+                                 attrs=mfma_reg_cap(dt, 64 * wm * wn, stages, "grouped"))
+                    out.append(("grouped_%s%s" % (DT_NAME[dt], "" if wide else "_el"), name, body, entry))
     # mixed grouped kernels: a tile program per product (kMixedTile), 2 x 2
     # wavefronts, LDS sized for the largest program
     for dt, fn in ((F32, "grouped_mixed_f32"), (BF16, "grouped_mixed_bf16")):
         bk = MIXED_BK[dt]
         bm, bn = max(MIXED_TILES, key=lambda t: t[0] * t[1])
         for stages in ((2, 1) if dt == F32 else (1,)):  # bf16: its 128 x 128 program spills with two stages
-            name = "pk_grouped_mixed_%s_w2x2_st%d" % (DT_NAME[dt], stages)
-            body = "pkk::%s<%d>(g);" % (fn, stages)
-            lds = max(mfma_lds(dt, m, n, bk, stages) for m, n in MIXED_TILES)
-            entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | MFMA_MIXED | (0 if stages == 2 else MFMA_SINGLE),
-                         dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=2, wn=2, threads=256, lds=lds,
-                         tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
-                         attrs=mfma_reg_cap(dt, 256, stages, "grouped"))
-            out.append(("grouped_mixed_%s" % DT_NAME[dt], name, body, entry))
+            for wide in (True, False):
+                name = "pk_grouped_mixed_%s_w2x2_st%d%s" % (DT_NAME[dt], stages, "" if wide else "_el")
+                body = "pkk::%s<%d, %s>(g);" % (fn, stages, "true" if wide else "false")
+                lds = max(mfma_lds(dt, m, n, bk, stages) for m, n in MIXED_TILES)
+                entry = dict(family=FAM_MFMA, variant=MFMA_GROUPED | MFMA_MIXED | (0 if stages == 2 else MFMA_SINGLE) |
+                             (0 if wide else MFMA_ELEMENT), dtype=dt, bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=2,
+                             wn=2, threads=256, lds=lds, tile_m=bm, tile_n=bn, args="pkk::GroupArgs g",
+                             attrs=mfma_reg_cap(dt, 256, stages, "grouped"))
+                out.append(("grouped_mixed_%s%s" % (DT_NAME[dt], "" if wide else "_el"), name, body, entry))
     return out
 
 

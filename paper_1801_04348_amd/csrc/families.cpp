@@ -449,7 +449,8 @@ const KernelEntry *find_instance(int family, int variant, int dtype, const std::
         if (variant & PK_VALU_GRAN) q[2] = 1;
         kind = variant & PK_VALU_NOLDS;
     } else {
-        kind = variant & (PK_MFMA_SINGLE | PK_MFMA_GROUPED);
+        // grouped instances come as a wide kernel and its element-load twin
+        kind = variant & (PK_MFMA_SINGLE | PK_MFMA_GROUPED | ((variant & PK_MFMA_GROUPED) ? PK_MFMA_ELEMENT : 0));
     }
     for (const auto &e : registry()) {
         if (e.family != family || e.dtype != dtype || e.variant != kind) continue;

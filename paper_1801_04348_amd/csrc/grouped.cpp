@@ -120,6 +120,12 @@ struct Assign {
 
 bool live(const GroupedOperands &o, int g) { return o.M[g] > 0 && o.N[g] > 0; }
 
+// The grouped kernel form a product runs in: the wide kernel when its rows
+// are aligned for 16-byte loads, else the element-load twin (PK_MFMA_ELEMENT).
+int form_of(int dtype, const GroupedOperands &o, int g) {
+    return o.K[g] > 0 && aligned_rows(dtype, o.A[g], o.lda[g], o.B[g], o.ldb[g]) ? 0 : (int)PK_MFMA_ELEMENT;
+}
+
 int check_operands(const GroupedOperands &o) {
     for (int g = 0; g < o.G; ++g) {
         if (o.M[g] < 0 || o.N[g] < 0 || o.K[g] < 0 || o.M[g] > kMaxDim || o.N[g] > kMaxDim || o.K[g] > kMaxDim)
@@ -176,11 +182,13 @@ bool assign_uniform(const pk_table *tbl, int dtype, const GroupedOperands &o, co
                     int stage, std::vector<Assign> *out) {
     if (!f.ok[pi]) return false;
     const auto &pt = f.part->fam.points[pi];
-    const KernelEntry *e = find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED, dtype, pt);
-    if (!e || !entry_fits(tbl->machine, *e)) return false;
+    const KernelEntry *forms[2] = {find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED, dtype, pt),
+                                   find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED | PK_MFMA_ELEMENT, dtype, pt)};
     out->assign(o.G, Assign{});
     for (int g = 0; g < o.G; ++g) {
         if (!live(o, g)) continue;
+        const KernelEntry *e = forms[form_of(dtype, o, g) ? 1 : 0];
+        if (!e || !entry_fits(tbl->machine, *e)) return false;
         Assign &a = (*out)[g];
         a.entry = e;
         a.tile_m = e->tile_m;
@@ -196,13 +204,18 @@ enum MixedRule { RULE_ESTIMATE = 0, RULE_WASTE_15, RULE_WASTE_35 };
 
 bool assign_mixed(const pk_table *tbl, int dtype, const GroupedOperands &o, const Feasibility &f, int stage,
                   int rule, std::vector<Assign> *out) {
-    const KernelEntry *e = mixed_entry(dtype, stage);
-    if (!e || !entry_fits(tbl->machine, *e)) return false;
-    KernelEntry progs[kMixedPrograms];
-    for (int p = 0; p < kMixedPrograms; ++p) progs[p] = as_program(*e, p);
+    const KernelEntry *forms[2] = {mixed_entry(dtype, stage), mixed_entry(dtype, stage | PK_MFMA_ELEMENT)};
+    KernelEntry progs_of[2][kMixedPrograms];
+    for (int w = 0; w < 2; ++w)
+        if (forms[w])
+            for (int p = 0; p < kMixedPrograms; ++p) progs_of[w][p] = as_program(*forms[w], p);
     out->assign(o.G, Assign{});
     for (int g = 0; g < o.G; ++g) {
         if (!live(o, g)) continue;
+        const int w = form_of(dtype, o, g) ? 1 : 0;
+        const KernelEntry *e = forms[w];
+        if (!e || !entry_fits(tbl->machine, *e)) return false;
+        const KernelEntry *progs = progs_of[w];
         int best = -1;
         double best_cost = 0.0, cost[kMixedPrograms];
         for (int p = 0; p < kMixedPrograms; ++p) {
@@ -264,11 +277,18 @@ void prefer_uniform(const pk_table *tbl, int dtype, const GroupedOperands &o, st
     if (!mixed) return;
     const int stage = mixed->variant & PK_MFMA_SINGLE;
     const std::vector<int64_t> pt = {kMixedTile[prog][0], kMixedTile[prog][1], pkk::kMixedBk[dtype], 2, 2};
-    const KernelEntry *e = find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED, dtype, pt);
-    if (!e || !entry_fits(tbl->machine, *e)) return;
+    const KernelEntry *forms[2] = {find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED, dtype, pt),
+                                   find_instance(PK_FAMILY_MFMA, stage | PK_MFMA_GROUPED | PK_MFMA_ELEMENT, dtype, pt)};
+    for (int g = 0; g < o.G; ++g) {
+        const Assign &a = (*as)[g];
+        if (!a.entry) continue;
+        const KernelEntry *e = forms[(a.entry->variant & PK_MFMA_ELEMENT) ? 1 : 0];
+        if (!e || !entry_fits(tbl->machine, *e)) return;
+    }
     for (int g = 0; g < o.G; ++g) {
         Assign &a = (*as)[g];
         if (!a.entry) continue;
+        const KernelEntry *e = forms[(a.entry->variant & PK_MFMA_ELEMENT) ? 1 : 0];
         a.entry = e;
         a.prog = 0;
         a.cost = tile_work_seconds(tbl->machine, *e, dtype, o.M[g], o.N[g], o.K[g]);
@@ -396,12 +416,21 @@ int assign_given(const pk_table *tbl, int dtype, const GroupedOperands &o, const
         if (!in_mixed) all_mixed = false;
     }
     if (first < 0) return PK_OK;
-    const KernelEntry *mixed = (!one_program && all_mixed) ? mixed_entry(dtype, stage[first]) : nullptr;
-    if (mixed && !entry_fits(tbl->machine, *mixed)) mixed = nullptr;
+    const KernelEntry *mixed_forms[2] = {nullptr, nullptr};
+    bool use_mixed = !one_program && all_mixed;
+    if (use_mixed)
+        for (int g = 0; g < o.G; ++g) {
+            if (!live(o, g)) continue;
+            const int w = form_of(dtype, o, g) ? 1 : 0;
+            if (!mixed_forms[w]) mixed_forms[w] = mixed_entry(dtype, stage[first] | (w ? PK_MFMA_ELEMENT : 0));
+            if (!mixed_forms[w] || !entry_fits(tbl->machine, *mixed_forms[w])) use_mixed = false;
+        }
     for (int g = 0; g < o.G; ++g) {
         if (!live(o, g)) continue;
         Assign &a = (*out)[g];
-        if (mixed) {
+        const int w = form_of(dtype, o, g) ? 1 : 0;
+        if (use_mixed) {
+            const KernelEntry *mixed = mixed_forms[w];
             a.entry = mixed;
             const KernelEntry x = as_program(*mixed, a.prog);
             a.tile_m = x.tile_m;
@@ -409,7 +438,8 @@ int assign_given(const pk_table *tbl, int dtype, const GroupedOperands &o, const
             a.cost = tile_work_seconds(tbl->machine, x, dtype, o.M[g], o.N[g], o.K[g]);
             continue;
         }
-        const KernelEntry *e = find_instance(PK_FAMILY_MFMA, stage[g] | PK_MFMA_GROUPED, dtype, pts[g]);
+        const KernelEntry *e =
+            find_instance(PK_FAMILY_MFMA, stage[g] | PK_MFMA_GROUPED | (w ? PK_MFMA_ELEMENT : 0), dtype, pts[g]);
         if (!e) return fail(PK_ERR_NOT_INSTANTIATED, "no grouped instance for product " + std::to_string(g));
         a.entry = e;
         a.prog = 0;

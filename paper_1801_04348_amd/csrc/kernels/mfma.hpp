@@ -803,27 +803,32 @@ __device__ __forceinline__ void walk_tiles(const GroupArgs &g, Tile &&tile) {
     }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+// WIDE: every product of the launch has rows aligned for 16-byte loads (the
+// host gives a launch only such products), so the kernel carries no
+// element-load path -- fewer registers, one more resident wavefront per SIMD
+// for the 64 x 64 programs; the element-load twin (WIDE = false) runs the
+// products whose rows are not aligned.
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE>
 __device__ __forceinline__ void grouped_f32(const GroupArgs &g) {
     using L = F32Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) float As[STAGES * L::A];
     __shared__ __attribute__((aligned(16))) float Bs[STAGES * L::B];
     walk_tiles(g, [&](const GroupDesc &d, int local) {
         const int tm = local / d.tiles_n, tn = local % d.tiles_n;
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, WIDE};
+        mfma_f32_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, WIDE, As, Bs, 0, (d.K + BK - 1) / BK);
     });
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int STAGES>
+template <int BM, int BN, int BK, int WM, int WN, int STAGES, bool WIDE>
 __device__ __forceinline__ void grouped_bf16(const GroupArgs &g) {
     using L = Bf16Lds<BM, BN, BK, STAGES>;
     __shared__ __attribute__((aligned(16))) unsigned short As[STAGES * L::A];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[STAGES * L::B];
     walk_tiles(g, [&](const GroupDesc &d, int local) {
         const int tm = local / d.tiles_n, tn = local % d.tiles_n;
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
-        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, d.vec != 0, As, Bs, 0, (d.K + BK - 1) / BK);
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, WIDE};
+        mfma_bf16_tile<BM, BN, BK, WM, WN, STAGES, true>(a, tm * BM, tn * BN, WIDE, As, Bs, 0, (d.K + BK - 1) / BK);
     });
 }
 
@@ -844,52 +849,52 @@ template <int STAGES> struct MixedLds {
                   Bf16Lds<kMixedTile[3][0], kMixedTile[3][1], kMixedBk[2], STAGES>::elems));
 };
 
-template <int P, int STAGES>
+template <int P, int STAGES, bool WIDE>
 __device__ __forceinline__ void mixed_f32_tile(const MmArgs &a, int local, int tiles_n, float *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
     const int tm = local / tiles_n, tn = local % tiles_n;
     using L = F32Lds<BM, BN, kMixedBk[0], STAGES>;
-    mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
+    mfma_f32_tile<BM, BN, kMixedBk[0], 2, 2, STAGES, true>(a, tm * BM, tn * BN, WIDE, lds,
                                                            lds + STAGES * L::A, 0,
                                                            (a.K + kMixedBk[0] - 1) / kMixedBk[0]);
 }
 
-template <int P, int STAGES>
+template <int P, int STAGES, bool WIDE>
 __device__ __forceinline__ void mixed_bf16_tile(const MmArgs &a, int local, int tiles_n, unsigned short *lds) {
     constexpr int BM = kMixedTile[P][0], BN = kMixedTile[P][1];
     const int tm = local / tiles_n, tn = local % tiles_n;
     using L = Bf16Lds<BM, BN, kMixedBk[2], STAGES>;
-    mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, a.vec != 0, lds,
+    mfma_bf16_tile<BM, BN, kMixedBk[2], 2, 2, STAGES, true>(a, tm * BM, tn * BN, WIDE, lds,
                                                             lds + STAGES * L::A, 0,
                                                             (a.K + kMixedBk[2] - 1) / kMixedBk[2]);
 }
 
-template <int STAGES>
+template <int STAGES, bool WIDE>
 __device__ __forceinline__ void grouped_mixed_f32(const GroupArgs &g) {
     static_assert(kMixedPrograms == 4, "one case per program");
     __shared__ __attribute__((aligned(16))) float lds[MixedLds<STAGES>::f32];
     walk_tiles(g, [&](const GroupDesc &d, int local) {
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, WIDE};
         switch (d.prog) {
-        case 0: mixed_f32_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
-        case 1: mixed_f32_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
-        case 2: mixed_f32_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
-        default: mixed_f32_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
+        case 0: mixed_f32_tile<0, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        case 1: mixed_f32_tile<1, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        case 2: mixed_f32_tile<2, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        default: mixed_f32_tile<3, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
         }
     });
 }
 
-template <int STAGES>
+template <int STAGES, bool WIDE>
 __device__ __forceinline__ void grouped_mixed_bf16(const GroupArgs &g) {
     static_assert(kMixedPrograms == 4, "one case per program");
     __shared__ __attribute__((aligned(16))) unsigned short lds[MixedLds<STAGES>::bf16];
     walk_tiles(g, [&](const GroupDesc &d, int local) {
-        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, d.vec};
+        const MmArgs a{d.A, d.B, d.C, d.lda, d.ldb, d.ldc, d.M, d.N, d.K, g.accumulate, WIDE};
         switch (d.prog) {
-        case 0: mixed_bf16_tile<0, STAGES>(a, local, d.tiles_n, lds); break;
-        case 1: mixed_bf16_tile<1, STAGES>(a, local, d.tiles_n, lds); break;
-        case 2: mixed_bf16_tile<2, STAGES>(a, local, d.tiles_n, lds); break;
-        default: mixed_bf16_tile<3, STAGES>(a, local, d.tiles_n, lds); break;
+        case 0: mixed_bf16_tile<0, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        case 1: mixed_bf16_tile<1, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        case 2: mixed_bf16_tile<2, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
+        default: mixed_bf16_tile<3, STAGES, WIDE>(a, local, d.tiles_n, lds); break;
         }
     });
 }

@@ -53,22 +53,24 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     // also reads 1 + s LDS words per s multiply-adds, which caps it near 24
     // multiply-adds per clock, rising slowly with s; the direct kernel is
     // bound by global/L1 reads (about one multiply-add per clock).
-    // int32 (fitted on 200 random int32 shapes): the tiled kernel's rate
-    // peaks at s = 2 and falls at s = 8, where each work-item holds eight
-    // running sums and their operands; relative rates 0.85, 1, 0.95, 0.70 for
-    // s = 1, 2, 4, 8 of the 32 multiply-adds per clock.
+    // int32 (fitted on the timings of every feasible candidate of 200 random
+    // int32 shapes, 140 to fit and 60 to check): the tiled kernel's relative
+    // rates 0.85, 0.9, 0.5, 0.7 for s = 1, 2, 4, 8 of the 32 multiply-adds
+    // per clock; the 2-D micro-tile program (four k of A and s columns of B
+    // per LDS read) up to 1.1 times that, or about 36 LDS words per clock.
     const double s = std::max(1, e.s);
     double mads = dtype == PK_I32 ? 32.0 : 64.0;
     if (e.family == PK_FAMILY_VALU2) {
         // 2-D micro-tiles: (s + sy) / (s sy) LDS words per multiply-add
-        // against about 24 words per clock, up to the ALU rate
+        // against the LDS's words per clock, up to the ALU rate
         const double sy = std::max(1, e.sy);
-        return 2.0 * lanes * std::min(mads * (dtype == PK_I32 ? 0.95 : 1.0), 24.0 * s * sy / (s + sy));
+        if (dtype == PK_I32) return 2.0 * lanes * std::min(mads * 1.1, 36.0 * s * sy / (s + sy));
+        return 2.0 * lanes * std::min(mads, 24.0 * s * sy / (s + sy));
     }
     if (e.variant & PK_VALU_NOLDS)
         mads = 1.0;
     else if (dtype == PK_I32)
-        mads *= e.s <= 1 ? 0.85 : e.s == 2 ? 1.0 : e.s <= 4 ? 0.95 : 0.70;
+        mads *= e.s <= 1 ? 0.85 : e.s == 2 ? 0.9 : e.s <= 4 ? 0.5 : 0.70;
     else
         mads = std::min(mads, 24.0 * std::pow(s / (1.0 + s), 0.25));
     return 2.0 * mads * lanes;
@@ -125,8 +127,8 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double flops_step = 2.0 * e.tile_m * e.tile_n * bk;
     const double waves_per_simd = (double)res * ((e.threads + wave - 1) / wave) / 4.0;
     const bool mfma = e.family == PK_FAMILY_MFMA;
-    const bool vi32 = !mfma && dtype == PK_I32;  // int32 VALU: its own fitted knee and barrier cost
-    const double occupancy = std::min(1.0, std::pow(waves_per_simd / (vi32 ? 6.0 : 3.0), mfma ? 0.4 : 0.25));
+    const bool vi32 = !mfma && dtype == PK_I32;  // int32 VALU: its own fitted barrier cost
+    const double occupancy = std::min(1.0, std::pow(waves_per_simd / 3.0, mfma ? 0.4 : 0.25));
     // MFMA: the tile's LDS words per output; VALU: workgroups of fewer than
     // 256 work-items lose in proportion
     const double eff = mfma ? 0.85 / (1.0 + 6.0 * (1.0 / e.tile_m + 1.0 / e.tile_n))
@@ -134,7 +136,7 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     const double rate = cu_rate(m, e, dtype) * clock * eff * occupancy;
     const double latency = mfma ? ((e.variant & PK_MFMA_SINGLE) ? 0.4e-6 : 0.3e-6) : 0.1e-6;
     // VALU K steps also pay their two barriers per resident workgroup
-    const double overhead = mfma ? 0.0 : (vi32 ? 0.025e-6 : 0.4e-6) * (double)res;
+    const double overhead = mfma ? 0.0 : (vi32 ? 0.1e-6 : 0.4e-6) * (double)res;
     // element loads instead of 16-byte loads (rows not aligned): measured
     // about 1.4x (f32) and 3.5x (bf16) slower per step, measured with the
     // same programs both ways at 2048^3 and 4096^3

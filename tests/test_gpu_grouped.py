@@ -57,6 +57,21 @@ def make_groups(G, seed, dtype, aligned_every=1, lo=16, hi=512):
     return dims, host, dev
 
 
+def row_forms(dtype, dev):
+    """The grouped kernel forms a plan over these operands needs: wide (rows
+    aligned for 16-byte loads: 16-byte aligned bases, leading dimensions
+    multiples of 4 float32 / 8 bfloat16 elements) and element loads; each
+    form runs as a launch of its own."""
+    vec = 8 if dtype == "bf16" else 4
+    forms = set()
+    for a, b, c in dev:
+        if a.shape[0] * b.shape[1] == 0:
+            continue
+        wide = a.shape[1] > 0 and all(t.data_ptr() % 16 == 0 and t.stride(0) % vec == 0 for t in (a, b))
+        forms.add(wide)
+    return forms
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_grouped_matches_oracle_and_single_launch(table, dtype):
     dims, host, dev = make_groups(96, seed=3, dtype=dtype, aligned_every=2, hi=300)
@@ -133,11 +148,11 @@ def test_exhaustive_plan_picks_a_fitting_program(table, dtype):
     As, Bs, Cs = zip(*dev)
     plan = pk.pk_grouped_plan_create(table, dtype, As, Bs, Cs, policy=pk.PK_POLICY_EXHAUSTIVE)
     n_launch, tiles, chosen = plan.info()
-    assert n_launch == 1
+    assert n_launch == len(row_forms(dtype, dev))  # one launch per row form
     names = {pk.pk_kernel_name(table, c, dtype) for c in chosen}
     say("%s exhaustive grouped pick: %s running %s" % (dtype, plan.kernels(), sorted(names)))
     if len(names) > 1:
-        assert plan.kernels()[0].startswith("pk_grouped_mixed_%s" % dtype)
+        assert all(k.startswith("pk_grouped_mixed_%s" % dtype) for k in plan.kernels())
     for c in Cs:
         c.fill_(float("nan"))              # the selection runs wrote C; start again
     plan.run()
@@ -208,7 +223,10 @@ def test_mixed_tiles_one_launch_bit_identical(table, dtype, stage):
     n_launch, tiles, chosen = plan.info()
     kernels = plan.kernels()
     say("%s stage %d mixed plan: %s, %d tiles" % (dtype, stage, kernels, tiles))
-    assert n_launch == 1 and kernels[0].startswith("pk_grouped_mixed_%s" % dtype), kernels
+    # one launch per row form (aligned rows, element loads), each the mixed kernel
+    assert n_launch == len(row_forms(dtype, dev)) == 2, kernels
+    assert all(k.startswith("pk_grouped_mixed_%s" % dtype) for k in kernels), kernels
+    assert sorted(k.endswith("_el") for k in kernels) == [False, True], kernels
     assert len({(c.bm, c.bn) for c in chosen}) == 4
     plan.run()
     torch.cuda.synchronize()
@@ -233,7 +251,7 @@ def test_mixed_tiles_accumulate_visits_each_tile_once(table):
     for c in Cs:
         c.zero_()
     plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, params=ps, accumulate=True)
-    assert plan.info()[0] == 1
+    assert plan.info()[0] == len(row_forms("f32", dev))
     plan.run()
     plan.run()
     torch.cuda.synchronize()
@@ -261,10 +279,21 @@ def test_two_stage_counts_get_launches_of_their_own(table):
 
 
 def test_case_plan_is_one_launch_and_learned_is_refused(table):
+    # aligned rows: one launch of the wide kernel; with some rows unaligned, a
+    # second launch of its element-load twin runs those products
+    dims, host, dev = make_groups(64, seed=29, dtype="f32", aligned_every=1, lo=16, hi=512)
+    As, Bs, Cs = zip(*dev)
+    plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs)
+    assert plan.info()[0] == 1 and not plan.kernels()[0].endswith("_el"), plan.kernels()
     dims, host, dev = make_groups(64, seed=29, dtype="f32", aligned_every=2, lo=16, hi=512)
     As, Bs, Cs = zip(*dev)
     plan = pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs)
-    assert plan.info()[0] == 1, plan.kernels()
+    assert len(row_forms("f32", dev)) == 2
+    assert plan.info()[0] == 2 and sorted(k.endswith("_el") for k in plan.kernels()) == [False, True], plan.kernels()
+    plan.run()
+    torch.cuda.synchronize()
+    for (a, b), (ad, bd, cd) in zip(host, dev):
+        assert rel_fro(cd.cpu().numpy(), om.matmul(a, b, "f32")) <= 1e-5
     with pytest.raises(pk.PkError) as e:
         pk.pk_grouped_plan_create(table, "f32", As, Bs, Cs, policy=pk.PK_POLICY_LEARNED)
     assert e.value.code == pk.PK_ERR_INVALID_ARG
