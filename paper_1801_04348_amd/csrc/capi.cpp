@@ -99,14 +99,16 @@ int64_t blocks_per_cu(const pk_machine &m, const KernelEntry &e) {
     return std::max<int64_t>(b, 1);
 }
 
-// One workgroup per tile for the MFMA programs, matrix addition and 1D
-// Jacobi (their tile loops then run once): for those HBM-bound programs the
-// hardware keeps the compute units full with fresh workgroups, which keeps
-// more loads in flight than a resident grid striding over the tiles (matrix
-// addition of order 2^14: 6.3 against 5.4 TB/s; Jacobi a few per cent).  The
-// other programs stride over the tiles with a resident grid.
+// One workgroup per tile for the MFMA programs, matrix addition, 1D Jacobi
+// and transposition (their tile loops then run once): for the HBM-bound
+// programs the hardware keeps the compute units full with fresh workgroups,
+// which keeps more loads in flight than a resident grid striding over the
+// tiles (matrix addition of order 2^14: 6.3 against 5.4 TB/s; transposition
+// of order 2^14, best program: 4.9 against 4.7 TB/s; Jacobi a few per cent).
+// The other programs stride over the tiles with a resident grid.
 static bool one_tile_per_workgroup(const KernelEntry &e) {
-    return e.family == PK_FAMILY_MFMA || e.family == PK_FAMILY_MADD || e.family == PK_FAMILY_JACOBI;
+    return e.family == PK_FAMILY_MFMA || e.family == PK_FAMILY_MADD || e.family == PK_FAMILY_JACOBI ||
+           e.family == PK_FAMILY_TRANSPOSE;
 }
 
 int64_t grid_of(const pk_machine &m, const KernelEntry &e, int64_t M, int64_t N) {
