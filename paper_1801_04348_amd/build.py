@@ -73,7 +73,7 @@ MFMA_F32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (128, 
             (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4)]
 MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128, 128, 64, 2, 2),
              (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4),
-             (256, 128, 32, 2, 2), (128, 256, 32, 2, 2)]
+             (256, 128, 32, 2, 2), (128, 256, 32, 2, 2), (256, 128, 64, 2, 2), (128, 256, 64, 2, 2)]
 
 
 def valu_lds(bx, by, s, nolds):
@@ -96,6 +96,11 @@ def mfma_reg_cap(dt, threads, stages, kind, bm=0, bn=0):
             (threads == 256 and bm * bn > 128 * 128):
         return "__attribute__((amdgpu_waves_per_eu(%d)))" % (threads // 128)
     return ""
+
+
+def twinless_bf16(bm, bn, bk, wm, wn):
+    """bfloat16 programs built without an element-load twin (it would spill)."""
+    return bm * bn >= 256 * 256 or (bk == 64 and wm * wn == 4 and bm * bn >= 128 * 256)
 
 
 def mfma_lds(dtype, bm, bn, bk, stages):
@@ -155,8 +160,10 @@ def instances():
                     entry_sk = dict(entry, variant=entry["variant"] | MFMA_SPLIT)
                     out.append(("mfma_%s_%d_sk" % (DT_NAME[dt], bm * 1000 + bn), name + "_sk", body_sk, entry_sk))
                 # the element-load twin, launched for rows not aligned for 16-byte
-                # loads (none for the largest bf16 tile, whose twin would spill)
-                if dt == BF16 and bm * bn >= 256 * 256:
+                # loads (none for the bf16 tiles whose twin would spill: the
+                # largest, and those of K tile 64 on four wavefronts with 128 x
+                # 256 outputs)
+                if dt == BF16 and twinless_bf16(bm, bn, bk, wm, wn):
                     continue
                 body_el = "pkk::%s<%d, %d, %d, %d, %d, %d, false>(a);" % (fn, bm, bn, bk, wm, wn, stages)
                 entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT,

@@ -94,7 +94,7 @@ const MfmaPoint kMfmaF32[] = {
 const MfmaPoint kMfmaBf16[] = {
     {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},  {128, 128, 64, 2, 2},
     {256, 128, 64, 4, 2}, {128, 256, 64, 2, 4}, {256, 256, 64, 4, 4}, {256, 128, 32, 2, 2},
-    {128, 256, 32, 2, 2},
+    {128, 256, 32, 2, 2}, {256, 128, 64, 2, 2}, {128, 256, 64, 2, 2},
 };
 
 struct Syms {

@@ -486,7 +486,7 @@ def packed_rows_wide(dtype, N: int, K: int) -> bool:
     """Whether packed operands (lda = K, ldb = N) from 16-byte aligned bases
     have rows aligned for the MFMA programs' wide loads."""
     if _dt(dtype) == PK_BF16:
-        return K % 8 == 0 and N % 2 == 0
+        return K % 8 == 0 and N % 8 == 0
     return K % 4 == 0 and N % 4 == 0
 
 

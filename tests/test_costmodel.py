@@ -117,6 +117,8 @@ def test_features_by_hand():
     assert np.array_equal(np.delete(f4, [9, 11, 12]), np.delete(f, [9, 11, 12]))
     assert pk.packed_rows_wide("f32", 3000, 512) and not pk.packed_rows_wide("f32", 3000, 513)
     assert pk.packed_rows_wide("bf16", 3000, 512) and not pk.packed_rows_wide("bf16", 3001, 512)
+    # bfloat16 rows of B need 16 bytes too: N a multiple of 8 elements
+    assert not pk.packed_rows_wide("bf16", 3004, 512) and not pk.packed_rows_wide("bf16", 3000, 516)
 
 
 @pytest.mark.gpu

@@ -164,6 +164,14 @@ def test_i32_full_range_wraps(table, fit):
 
 
 # ---------------------------------------------------------------- MFMA leaves
+def twinless(desc, dtype, pt, v):
+    """The MFMA program has no element-load twin among the compiled instances."""
+    name = "pk_mfma_%s_%dx%dx%d_w%dx%d_st%d" % ((dtype,) + tuple(pt) + (1 if v & pk.PK_MFMA_SINGLE else 2,))
+    names = {e["name"] for e in desc["instances"]}
+    assert name in names, name
+    return name + "_el" not in names
+
+
 def mfma_points(desc, dtype):
     pts = []
     for part in desc["parts"]:
@@ -338,7 +346,7 @@ def test_unaligned_rows_take_element_loads(table, fit, desc, dtype):
     for pt in mfma_points(desc, dtype):
         for v in MFMA_VARIANTS:
             say("mfma %s unaligned %s variant %d" % (dtype, pt, v))
-            if dtype == "bf16" and pt[0] * pt[1] >= 256 * 256 and fit(1, dtype, v, pt):
+            if twinless(desc, dtype, pt, v) and fit(1, dtype, v, pt):
                 # no element-load form of this tile: the CASE choice for these operands runs
                 C = run(table, mfma_params(pt, v), dtype, Au, Bu, M, N)
                 assert rel_fro(C.numpy(), ref) <= tol, (pt, v)
@@ -370,7 +378,7 @@ def test_tiny_unaligned_shapes_every_twin(table, fit, desc, dtype, M, N, K):
     tol = F32_TOL if dtype == "f32" else BF16_TOL
     for pt in mfma_points(desc, dtype):
         for v in MFMA_VARIANTS:
-            if not fit(1, dtype, v, pt) or (dtype == "bf16" and pt[0] * pt[1] >= 256 * 256):
+            if not fit(1, dtype, v, pt) or twinless(desc, dtype, pt, v):
                 continue
             say("mfma %s twin %s variant %d on %dx%dx%d" % (dtype, pt, v, M, N, K))
             C = run(table, mfma_params(pt, v), dtype, dev(A), dev(B), M, N)

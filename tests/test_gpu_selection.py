@@ -79,14 +79,25 @@ def check(table, p, dtype, A, B, ref, Ad=None, Bd=None):
         assert err <= TOL[dtype], (name, err)
 
 
-def feasible_count(table, dtype):
-    """Points of the product families whose case-table lookup gives a leaf."""
+def feasible_count(table, dtype, wide=True):
+    """Points of the product families whose case-table lookup gives a leaf;
+    on rows not aligned for 16-byte loads (wide False) without the MFMA
+    programs that have no element-load form."""
     d = pk.pk_case_table_describe(table)
+    names = {e["name"] for e in d["instances"]}
     n = 0
     for part in d["parts"]:
         if part["family"] in (pk.PK_FAMILY_VALU, pk.PK_FAMILY_VALU2, pk.PK_FAMILY_MFMA) and \
                 part["dtype"] == pk.DTYPES[dtype]:
-            n += sum(1 for leaf in part["first_leaf"] if leaf >= 0)
+            for pt, leaf in zip(part["points"], part["first_leaf"]):
+                if leaf < 0:
+                    continue
+                if part["family"] == pk.PK_FAMILY_MFMA and not wide:
+                    st = 1 if part["solution"]["leaves"][leaf]["variant"] & pk.PK_MFMA_SINGLE else 2
+                    name = "pk_mfma_%s_%dx%dx%d_w%dx%d_st%d" % ((dtype,) + tuple(pt) + (st,))
+                    if name + "_el" not in names:
+                        continue
+                n += 1
     return n
 
 
@@ -103,11 +114,13 @@ def test_measure_and_exhaustive_pick(table, dtype, shape):
     C = out_tensor(dtype, M, N)
     say("pk_measure %s %s" % (dtype, shape))
     res = pk.pk_measure(table, dtype, M, N, K, Ad, Bd, C)
-    # every feasible (leaf, E) is timed: aligned operands, so every point
-    # with a leaf is a candidate, run whole and (MFMA programs, few tiles)
-    # split along K
+    # every feasible (leaf, E) is timed: every point with a leaf is a
+    # candidate (on unaligned rows, those MFMA programs that have an
+    # element-load form), run whole and (MFMA programs, few tiles) split
+    # along K
     whole = [p for p, _ in res if p.ks <= 1]
-    assert len(whole) == feasible_count(table, dtype), (len(whole), feasible_count(table, dtype))
+    wide = pk.packed_rows_wide(dtype, N, K)
+    assert len(whole) == feasible_count(table, dtype, wide), (len(whole), feasible_count(table, dtype, wide))
     assert all(p.family == pk.PK_FAMILY_MFMA for p, _ in res if p.ks > 1)
     secs = np.array([s for _, s in res])
     assert np.all(np.isfinite(secs)) and np.all(secs > 0), secs

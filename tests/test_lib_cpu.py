@@ -439,7 +439,10 @@ def test_every_mfma_program_has_an_element_load_twin(gfx_desc):
               if e["family"] == en.MFMA and not e["variant"] & (2 | en.ELEMENT | pk.PK_MFMA_SPLIT)]
     for e in single:
         twin = inst.get(e["name"] + "_el")
-        if e["dtype"] == 2 and e["bm"] * e["bn"] >= 256 * 256:
+        # bf16 tiles built without a twin (it would spill): the largest, and
+        # those of K tile 64 on four wavefronts with 128 x 256 outputs
+        if e["dtype"] == 2 and (e["bm"] * e["bn"] >= 256 * 256 or
+                                (e["bk"] == 64 and e["wm"] * e["wn"] == 4 and e["bm"] * e["bn"] >= 128 * 256)):
             assert twin is None
             continue
         assert twin is not None and twin["variant"] == e["variant"] | en.ELEMENT, e["name"]
