@@ -70,7 +70,8 @@ TR_BX = (16, 32, 64)
 TR_BY = (4, 8, 16, 32)
 TR_S = (1, 2, 4, 8)
 MFMA_F32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (128, 128, 32, 2, 2),
-            (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4)]
+            (256, 128, 32, 4, 2), (128, 256, 32, 2, 4), (256, 256, 32, 4, 4), (256, 128, 32, 2, 2),
+            (128, 256, 32, 2, 2), (256, 128, 16, 4, 2), (128, 256, 16, 2, 4)]
 MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128, 128, 64, 2, 2),
              (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4),
              (256, 128, 32, 2, 2), (128, 256, 32, 2, 2), (256, 128, 64, 2, 2), (128, 256, 64, 2, 2)]
@@ -154,8 +155,10 @@ def instances():
                 out.append(("mfma_%s_%d" % (DT_NAME[dt], bm * 1000 + bn), name, body, entry))
                 # the split-along-K form of the wide program (workgroups of up
                 # to 512 work-items; not the single-stage float32 programs of
-                # 512, whose 128-register cap it would exceed)
-                if 64 * wm * wn <= 512 and not (dt == F32 and 64 * wm * wn == 512 and stages == 1):
+                # 512, whose 128-register cap it would exceed, nor those of
+                # 128 x 256 outputs or more, whose split form would spill)
+                if 64 * wm * wn <= 512 and not (dt == F32 and stages == 1 and
+                                                (64 * wm * wn == 512 or bm * bn >= 128 * 256)):
                     body_sk = "pkk::%s<%d, %d, %d, %d, %d, %d, true, true>(a);" % (fn, bm, bn, bk, wm, wn, stages)
                     entry_sk = dict(entry, variant=entry["variant"] | MFMA_SPLIT)
                     out.append(("mfma_%s_%d_sk" % (DT_NAME[dt], bm * 1000 + bn), name + "_sk", body_sk, entry_sk))

@@ -89,7 +89,8 @@ const int kTrS[] = {1, 2, 4, 8};
 
 const MfmaPoint kMfmaF32[] = {
     {64, 64, 32, 2, 2},   {128, 64, 32, 2, 2},  {64, 128, 32, 2, 2},  {128, 128, 32, 2, 2},
-    {256, 128, 32, 4, 2}, {128, 256, 32, 2, 4}, {256, 256, 32, 4, 4},
+    {256, 128, 32, 4, 2}, {128, 256, 32, 2, 4}, {256, 256, 32, 4, 4}, {256, 128, 32, 2, 2},
+    {128, 256, 32, 2, 2}, {256, 128, 16, 4, 2}, {128, 256, 16, 2, 4},
 };
 const MfmaPoint kMfmaBf16[] = {
     {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},  {128, 128, 64, 2, 2},
