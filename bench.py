@@ -219,8 +219,15 @@ def grouped_section(tbl, pk, torch, inputs, dtype, reps=5):
     roof = float(np.sum(np.maximum(2.0 * np.prod(dims.astype(np.float64), axis=1) / peak, per_bytes / 8e12)))
 
     def timed(fn):
-        fn()
-        torch.cuda.synchronize()
+        # a quarter second of untimed runs first: the clock settles under the
+        # load (a plan timed right after the device sat idle runs 10-20 %
+        # slower than in steady state)
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            torch.cuda.synchronize()
+            if time.perf_counter() - t0 >= 0.25:
+                break
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
