@@ -4,7 +4,9 @@ Each runs a few untimed repetitions of one workload on cuda:0, bracketed by
 the benchmark's calibration copies (a float32 add of zero over 256 MiB,
 three times first, then once right before and once right after the
 repetitions; profwindow.timed_window selects the dispatches between the last
-two), so a rocprofv3 run over it reports the workload's kernels alone:
+two), so a rocprofv3 run over it reports the workload's kernels alone.
+Before the window the workload runs for --warm seconds (0.25), so the
+window sees the clock the workload settles at:
 
     python3 -m paper_1801_04348_amd.workloads grouped --dtype f32 --reps 5
     python3 -m paper_1801_04348_amd.workloads dense --dtype bf16 --n 4096 --reps 20
@@ -62,6 +64,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--policy", default="case", choices=["case", "exhaustive"])
+    ap.add_argument("--warm", type=float, default=0.25, help="seconds of untimed runs before the first marker")
     ap.add_argument("--program", default=None,
                     help="dense: run this MFMA program instead of the policy's pick, "
                          "as bm,bn,bk,wm,wn[,variant] (variant 1: one LDS stage)")
@@ -112,6 +115,12 @@ def main():
             pk.pk_matmul(tbl, p, args.dtype, A, B, C)
         run()
     torch.cuda.synchronize()
+    # untimed runs until the clock has settled under the load
+    import time
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < args.warm:
+        run()
+        torch.cuda.synchronize()
     marker()
     for _ in range(args.reps):
         run()
