@@ -20,7 +20,9 @@ enumeration over a grid of machines and the whole program-parameter domain:
 * MFMA family: program parameters bm, bn, bk, wm, wn; programs {} (two LDS
   stages) and {single} (one).  One stage holds, in float32, an A tile bm x
   (bk + 4) and a B tile bk x (bn + 4); in bfloat16 an A tile bm x (bk + 8) and
-  a B tile bk x (bn + 32); threads: 64 * wm * wn.
+  a B tile bk x (bn + 32); in int32 (four one-byte digit planes per operand,
+  rows of bk + 16 bytes) 4 * (bm + bn) * (bk + 16) bytes; threads:
+  64 * wm * wn.
 * Transposition family (Section 5.2, Fig. 7): program parameters bx (the
   paper's B1), by (B0), s; programs as in the VALU family; the cached program
   holds one (by * s') x bx tile padded by one element per row: 4 * (by * s')
@@ -131,6 +133,8 @@ def mfma_lds(dtype: int, variant: int, bm: int, bn: int, bk: int) -> int:
     stages = 1 if variant & SINGLE else 2
     if dtype == F32:
         one = 4 * (bm * (bk + 4) + bk * (bn + 4))
+    elif dtype == I32:
+        one = 4 * (bm + bn) * (bk + 16)
     else:
         one = 2 * (bm * (bk + 8) + bk * (bn + 32))
     return stages * one
@@ -309,8 +313,8 @@ def oracle_family(family: int, dtype: int, points: List[Tuple[int, ...]], inst: 
         program = ["bm", "bn", "bk", "wm", "wn"]
         strategies = [co.Strategy("single", False, frozenset({"r_Z", "r_V"}))]
         names = {0: "rho_two_stage", SINGLE: "rho_one_stage"}
-        one = (co.parse_poly("4*(bm*(bk+4) + bk*(bn+4))") if dtype == F32
-               else co.parse_poly("2*(bm*(bk+8) + bk*(bn+32))"))
+        one = co.parse_poly({F32: "4*(bm*(bk+4) + bk*(bn+4))", I32: "4*(bm+bn)*(bk+16)"}.get(
+            dtype, "2*(bm*(bk+8) + bk*(bn+32))"))
 
         def lds_poly(applied):
             return one if "single" in applied else co.Poly.const(2) * one

@@ -76,6 +76,9 @@ MFMA_BF16 = [(64, 64, 64, 2, 2), (128, 64, 64, 2, 2), (64, 128, 64, 2, 2), (128,
              (256, 128, 64, 4, 2), (128, 256, 64, 2, 4), (256, 256, 64, 4, 4),
              (256, 128, 32, 2, 2), (128, 256, 32, 2, 2), (256, 128, 64, 2, 2), (128, 256, 64, 2, 2)]
 
+# int32 on the int8 matrix cores (four signed digit planes per operand)
+MFMA_I32 = [(64, 64, 32, 2, 2), (128, 64, 32, 2, 2), (64, 128, 32, 2, 2), (64, 64, 64, 2, 2)]
+
 
 def valu_lds(bx, by, s, nolds):
     return 0 if nolds else 4 * (by * (by + 1) + by * bx * s)
@@ -107,6 +110,8 @@ def twinless_bf16(bm, bn, bk, wm, wn):
 def mfma_lds(dtype, bm, bn, bk, stages):
     if dtype == F32:
         return stages * 4 * (bm * (bk + 4) + bk * (bn + 4))
+    if dtype == I32:
+        return stages * 4 * (bm + bn) * (bk + 16)
     return stages * 2 * (bm * (bk + 8) + bk * (bn + 32))
 
 
@@ -174,6 +179,23 @@ def instances():
                 # (a translation unit of its own: compiled beside the wide kernel
                 # it changes the wide kernel's instruction schedule, measurably)
                 out.append(("mfma_%s_%d_el" % (DT_NAME[dt], bm * 1000 + bn), name + "_el", body_el, entry_el))
+    # int32 on the int8 matrix cores: a wide form (16-byte loads of A where its
+    # rows are aligned) and its element-load twin; no split form.  Wave tiles
+    # of two 32 x 32 blocks hold 128 accumulator registers (four sums per
+    # block): those programs are capped at 256 registers a lane, the block
+    # budget of 65536 over 256 work-items.
+    for (bm, bn, bk, wm, wn) in MFMA_I32:
+        cap = "__attribute__((amdgpu_waves_per_eu(2)))" if bm * bn > 64 * 64 else ""
+        for stages in (2, 1):
+            name = "pk_mfma_i32_%dx%dx%d_w%dx%d_st%d" % (bm, bn, bk, wm, wn, stages)
+            entry = dict(family=FAM_MFMA, variant=0 if stages == 2 else MFMA_SINGLE, dtype=I32,
+                         bx=0, by=0, s=0, bk=bk, bm=bm, bn=bn, wm=wm, wn=wn, threads=64 * wm * wn,
+                         lds=mfma_lds(I32, bm, bn, bk, stages), tile_m=bm, tile_n=bn, attrs=cap)
+            body = "pkk::mfma_i32<%d, %d, %d, %d, %d, %d>(a);" % (bm, bn, bk, wm, wn, stages)
+            out.append(("mfma_i32", name, body, entry))
+            body_el = "pkk::mfma_i32<%d, %d, %d, %d, %d, %d, false>(a);" % (bm, bn, bk, wm, wn, stages)
+            entry_el = dict(entry, variant=entry["variant"] | MFMA_ELEMENT)
+            out.append(("mfma_i32_el", name + "_el", body_el, entry_el))
     # transposition: tiled and direct programs (bit copies of 4-byte elements)
     for bx in TR_BX:
         for by in TR_BY:

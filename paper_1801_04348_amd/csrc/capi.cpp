@@ -264,7 +264,7 @@ int pk_case_table_build(int device, const pk_machine *override_or_null, pk_table
                 pk_table::Part part;
                 part.family = family;
                 part.dtype = dtype;
-                const bool ok = family == PK_FAMILY_MFMA      ? (dtype == PK_F32 || dtype == PK_BF16)
+                const bool ok = family == PK_FAMILY_MFMA      ? true
                                 : family == PK_FAMILY_POLYDIV ? dtype == PK_I32
                                                               : (dtype == PK_F32 || dtype == PK_I32);
                 part.supported = ok;

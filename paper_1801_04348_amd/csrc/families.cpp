@@ -92,6 +92,9 @@ const MfmaPoint kMfmaF32[] = {
     {256, 128, 32, 4, 2}, {128, 256, 32, 2, 4}, {256, 256, 32, 4, 4}, {256, 128, 32, 2, 2},
     {128, 256, 32, 2, 2}, {256, 128, 16, 4, 2}, {128, 256, 16, 2, 4},
 };
+const MfmaPoint kMfmaI32[] = {
+    {64, 64, 32, 2, 2}, {128, 64, 32, 2, 2}, {64, 128, 32, 2, 2}, {64, 64, 64, 2, 2},
+};
 const MfmaPoint kMfmaBf16[] = {
     {64, 64, 64, 2, 2},   {128, 64, 64, 2, 2},  {64, 128, 64, 2, 2},  {128, 128, 64, 2, 2},
     {256, 128, 64, 4, 2}, {128, 256, 64, 2, 4}, {256, 256, 64, 4, 4}, {256, 128, 32, 2, 2},
@@ -316,7 +319,8 @@ Family matmul_family(int family, int dtype) {
         return f;
     }
     if (family == PK_FAMILY_MFMA) {
-        if (dtype != PK_F32 && dtype != PK_BF16) throw std::runtime_error("MFMA family: f32 and bf16 only");
+        if (dtype != PK_F32 && dtype != PK_BF16 && dtype != PK_I32)
+            throw std::runtime_error("MFMA family: f32, bf16 and i32 only");
         const int bm = add_sym(f, "bm", SYM_PROGRAM), bn = add_sym(f, "bn", SYM_PROGRAM),
                   bk = add_sym(f, "bk", SYM_PROGRAM), wm = add_sym(f, "wm", SYM_PROGRAM),
                   wn = add_sym(f, "wn", SYM_PROGRAM);
@@ -324,12 +328,17 @@ Family matmul_family(int family, int dtype) {
         f.point_syms = {bm, bn, bk, wm, wn};
         if (dtype == PK_F32)
             for (const auto &p : kMfmaF32) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
+        else if (dtype == PK_I32)
+            for (const auto &p : kMfmaI32) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
         else
             for (const auto &p : kMfmaBf16) f.points.push_back({p.bm, p.bn, p.bk, p.wm, p.wn});
         // one stage: f32  4 * (bm * (bk + 4) + bk * (bn + 4))
         //            bf16 2 * (bm * (bk + 8) + bk * (bn + 32))
-        Poly stage = dtype == PK_F32 ? P(4) * (S(bm) * (S(bk) + P(4)) + S(bk) * (S(bn) + P(4)))
-                                     : P(2) * (S(bm) * (S(bk) + P(8)) + S(bk) * (S(bn) + P(32)));
+        //            i32  4 * (bm + bn) * (bk + 16)  (four one-byte digit planes
+        //                 per operand, rows bk + 16 bytes apart)
+        Poly stage = dtype == PK_F32   ? P(4) * (S(bm) * (S(bk) + P(4)) + S(bk) * (S(bn) + P(4)))
+                     : dtype == PK_I32 ? P(4) * (S(bm) + S(bn)) * (S(bk) + P(16))
+                                       : P(2) * (S(bm) * (S(bk) + P(8)) + S(bk) * (S(bn) + P(32)));
         CounterDef rz{"r_Z", false, m.Z, nullptr};
         rz.value = [=](uint32_t ap) { return (ap & PK_MFMA_SINGLE) ? stage : P(2) * stage; };
         CounterDef rv{"r_V", false, m.V, nullptr};

@@ -47,7 +47,9 @@ double cu_rate(const pk_machine &m, const KernelEntry &e, int dtype) {
     const int threads = e.threads;
     const int wave = m.wave > 0 ? m.wave : 64;
     const double lanes = (double)threads / (double)(wave * ((threads + wave - 1) / wave));
-    if (e.family == PK_FAMILY_MFMA) return dtype == PK_BF16 ? 2048.0 : 256.0;
+    // MFMA: float32 256, bfloat16 2048; int32 on the int8 matrix cores 8192
+    // int8 operations per clock, ten int8 products per int32 one
+    if (e.family == PK_FAMILY_MFMA) return dtype == PK_BF16 ? 2048.0 : dtype == PK_I32 ? 819.2 : 256.0;
     // VALU: 64 lanes x 4 SIMDs / 4 cycles = 64 multiply-adds per clock for
     // float32; int32 multiply-adds run at half of that (measured).  The tiled kernel
     // also reads 1 + s LDS words per s multiply-adds, which caps it near 24
@@ -140,7 +142,7 @@ double estimate_seconds(const pk_machine &m, const KernelEntry &e, int dtype, in
     // element loads instead of 16-byte loads (rows not aligned): measured
     // about 1.4x (f32) and 3.5x (bf16) slower per step, measured with the
     // same programs both ways at 2048^3 and 4096^3
-    const double narrow = (mfma && !wide) ? (dtype == PK_BF16 ? 3.5 : 1.4) : 1.0;
+    const double narrow = (mfma && !wide) ? (dtype == PK_BF16 ? 3.5 : dtype == PK_I32 ? 1.2 : 1.4) : 1.0;
     const double compute =
         narrow * (double)rounds * ksteps * (std::max((double)res * flops_step / rate, latency) + overhead);
     const double es = elem_bytes(dtype);

@@ -287,8 +287,9 @@ def test_matmul_argument_errors_without_gpu(gfx_table):
     assert rc == pk.PK_OK
     rc = L.pk_matmul(None, None, 0, None, 4, None, 4, None, 4, 4, 4, 4, 0, None)
     assert rc == pk.PK_ERR_INVALID_ARG
-    bad = pk.params(family=pk.PK_FAMILY_MFMA, bm=64, bn=64, bk=32, wm=2, wn=2)
-    rc = L.pk_matmul(gfx_table.handle, bad, pk.PK_I32, 16, 4, 16, 4, 16, 4, 4, 4, 4, 0, None)
+    # the VALU programs have no bfloat16 form
+    bad = pk.params(family=pk.PK_FAMILY_VALU, bx=16, by=16, s=1)
+    rc = L.pk_matmul(gfx_table.handle, bad, pk.PK_BF16, 16, 4, 16, 4, 16, 4, 4, 4, 4, 0, None)
     assert rc == pk.PK_ERR_UNSUPPORTED_DTYPE
 
 
@@ -460,7 +461,7 @@ def test_every_mfma_program_has_an_element_load_twin(gfx_desc):
         for sym, vals in part["tables"].items():
             v = en.SINGLE if "one" in sym else 0
             for pt, val in zip(part["points"], vals):
-                e = inst["pk_mfma_%s_%dx%dx%d_w%dx%d_st%d" % ({0: "f32", 2: "bf16"}[part["dtype"]], *pt,
+                e = inst["pk_mfma_%s_%dx%dx%d_w%dx%d_st%d" % ({0: "f32", 1: "i32", 2: "bf16"}[part["dtype"]], *pt,
                                                              1 if v else 2)]
                 own = en.regs_per_block(e["vgpr"], e["agpr"], e["threads"])
                 assert val == data.regs(en.MFMA, part["dtype"], v, tuple(pt)) and val >= own
