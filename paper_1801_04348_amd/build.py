@@ -319,7 +319,7 @@ def generate():
     tus = []
     for grp, items in sorted(groups.items()):
         lines = ["// generated by build.py -- kernel instances of group %s" % grp,
-                 "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"',
+                 "#include <hip/hip_runtime.h>", '#include "kernels/valu.hpp"', '#include "kernels/mfma.hpp"', '#include "kernels/mfma_i32.hpp"',
                  '#include "kernels/transpose.hpp"', '#include "kernels/madd.hpp"',
                  '#include "kernels/jacobi.hpp"', '#include "kernels/polydiv.hpp"', ""]
         for name, body, entry in items:

@@ -2,8 +2,9 @@
 the HBM roofline (8 TB/s) of its compulsory traffic: matrix transposition
 (Section 5.2, Table 3's order 2^14), matrix addition (Section 1), 1D Jacobi
 (Section 5, Table 2's length 2^15 + 2, and 2^28 + 2) and polynomial division
-(Section 5, Table 4's sizes), and the VALU matmul programs against their
-measured arithmetic ceiling.  Each reports the CASE pick and the
+(Section 5, Table 4's sizes), and the matmul programs of int32 1024^3 and
+float32 256^3 against the roofline of their unit (the measured VALU ceiling;
+for int32 on the matrix cores, the int8 peak over ten).  Each reports the CASE pick and the
 exhaustively-best leaf.  bench.py includes them in its JSON line; alone:
 
     python -m paper_1801_04348_amd.sidebench      # one JSON line
@@ -136,27 +137,34 @@ def transpose_section(tbl, pk, torch, inputs, n=16384, reps=10):
 
 
 def valu_section(tbl, pk, torch, inputs, reps=20):
-    """The VALU matmul programs against their measured ceiling
-    (pk_probe_valu_rate): int32 1024^3 with small-integer entries and float32
-    256^3, CASE pick, LEARNED pick (where the table has a model for the
-    type) and exhaustively-best leaf, in operations per second (2 M N K per
-    product)."""
+    """The matmul programs of int32 1024^3 (small-integer entries) and float32
+    256^3: CASE pick, LEARNED pick (where the table has a model for the type),
+    exhaustively-best program, and the fastest VALU program, in operations
+    per second (2 M N K per product).  Each is set against the roofline of
+    its unit: the measured VALU multiply-add ceiling (pk_probe_valu_rate) for
+    the VALU programs; for the int32 MFMA programs the int8 matrix cores'
+    5.0 POP/s over the ten int8 products each int32 one takes, 500 TOP/s."""
+    mfma_i32_peak = 5.0e15 / 10
     out = {"ceiling_f32_tflops": round(pk.pk_probe_valu_rate(tbl, "f32") / 1e12, 2),
-           "ceiling_i32_tops": round(pk.pk_probe_valu_rate(tbl, "i32") / 1e12, 2)}
+           "ceiling_i32_tops": round(pk.pk_probe_valu_rate(tbl, "i32") / 1e12, 2),
+           "mfma_i32_roofline_tops": round(mfma_i32_peak / 1e12, 1)}
     for dtype, n, gen in (("i32", 1024, inputs.small_int_i32), ("f32", 256, inputs.uniform_f32)):
         A = gen((n, n), seed=0).cuda()
         B = gen((n, n), seed=1).cuda()
         C = torch.empty((n, n), dtype=A.dtype, device="cuda")
         ceiling = out["ceiling_%s_%s" % (dtype, "tops" if dtype == "i32" else "tflops")] * 1e12
-        row = {}
+        picks = []
         for name, pol in (("case", pk.PK_POLICY_CASE), ("learned", pk.PK_POLICY_LEARNED),
                           ("best", pk.PK_POLICY_EXHAUSTIVE)):
             try:
-                p = pk.pk_select(tbl, dtype, n, n, n, pol)
+                picks.append((name, pk.pk_select(tbl, dtype, n, n, n, pol)))
             except pk.PkError as e:
-                if e.code == pk.PK_ERR_COST_MODEL:  # no model for this type on the table
-                    continue
-                raise
+                if e.code != pk.PK_ERR_COST_MODEL:  # no model for this type on the table
+                    raise
+        valu = [(p, t) for p, t in pk.pk_measure(tbl, dtype, n, n, n, A, B, C) if p.family != pk.PK_FAMILY_MFMA]
+        picks.append(("best_valu", min(valu, key=lambda pt: pt[1])[0]))
+        row = {}
+        for name, p in picks:
             pk.pk_matmul(tbl, p, dtype, A, B, C)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -167,8 +175,9 @@ def valu_section(tbl, pk, torch, inputs, reps=20):
             torch.cuda.synchronize()
             s = e0.elapsed_time(e1) / reps * 1e-3
             rate = 2.0 * n ** 3 / s
+            roof = mfma_i32_peak if p.family == pk.PK_FAMILY_MFMA and dtype == "i32" else ceiling
             row[name] = {"kernel": pk.pk_kernel_name(tbl, p, dtype), "us": round(s * 1e6, 1),
-                         "tops": round(rate / 1e12, 2), "frac_of_ceiling": round(rate / ceiling, 4)}
+                         "tops": round(rate / 1e12, 2), "frac_of_roofline": round(rate / roof, 4)}
         out["%s_%d" % (dtype, n)] = row
     return out
 
