@@ -13,8 +13,9 @@ window sees the clock the workload settles at:
 
 `grouped`: the 4096 uneven products of the grouped benchmark (M, N, K each
 round(exp(U(ln 16, ln 512))) from seed 0), one plan, run eagerly `reps`
-times.  `dense`: one square product of order n, CASE pick (or --policy, or
-the MFMA program --program names).
+times (f32 or bf16).  `dense`: one square product of order n (f32, bf16, or
+full-range i32), CASE pick (or --policy, or the MFMA program --program
+names).
 """
 from __future__ import annotations
 
@@ -60,7 +61,7 @@ def grouped_operands(torch, inputs, dtype, G=4096, seed=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", choices=["grouped", "dense"])
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "i32"])
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--policy", default="case", choices=["case", "exhaustive"])
@@ -99,10 +100,13 @@ def main():
         if args.dtype == "bf16":
             A = inputs.bf16_bits(inputs.uniform_f32((n, n), seed=21)).cuda()
             B = inputs.bf16_bits(inputs.uniform_f32((n, n), seed=22)).cuda()
+        elif args.dtype == "i32":
+            A = inputs.full_range_i32((n, n), seed=21).cuda()
+            B = inputs.full_range_i32((n, n), seed=22).cuda()
         else:
             A = inputs.uniform_f32((n, n), seed=21).cuda()
             B = inputs.uniform_f32((n, n), seed=22).cuda()
-        C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        C = torch.empty((n, n), dtype=torch.int32 if args.dtype == "i32" else torch.float32, device="cuda")
         if args.program:
             v = [int(x) for x in args.program.split(",")]
             p = pk.params(family=pk.PK_FAMILY_MFMA, bm=v[0], bn=v[1], bk=v[2], wm=v[3], wn=v[4],
