@@ -95,11 +95,14 @@ __device__ __forceinline__ void mfma_i32_tile(const MmArgs &a, const int row0, c
     for (int u = 0; u < AQ; ++u)
         arow[u] = A + (int64_t)min(row0 + (tid + u * NT) / (BK / 4), M - 1) * a.lda + akq;
     const int64_t ldb = a.ldb, ldb2 = 2 * ldb, ldb3 = 3 * ldb;
-    const int bk0 = 4 * (tid / BN);  // k offset of the work-item's first B quad in a step
+    // B: a work-item's BQ quads are consecutive in k (4 BQ of them from bk0),
+    // so each digit plane takes one 4 BQ-byte LDS store per step: with one
+    // four-byte store per quad, the 64 lanes' stores (one column each, rows
+    // BK + 16 bytes apart) fell four to a bank
+    const int bk0 = 4 * BQ * (tid / BN);
     gptr<int32_t> bcol[BQ];
 #pragma unroll
-    for (int u = 0; u < BQ; ++u)
-        bcol[u] = B + (int64_t)(bk0 + u * 4 * (NT / BN)) * ldb + min(col0 + tid % BN, N - 1);
+    for (int u = 0; u < BQ; ++u) bcol[u] = B + (int64_t)(bk0 + 4 * u) * ldb + min(col0 + tid % BN, N - 1);
 
     i32x4 ra[AQ], rb[BQ];
     auto gload = [&](int k0) {
@@ -124,7 +127,7 @@ __device__ __forceinline__ void mfma_i32_tile(const MmArgs &a, const int row0, c
 #pragma unroll
                 for (int e = 0; e < 4; ++e) rb[u][e] = *q[e];
             } else {
-                const int k = k0 + bk0 + u * 4 * (NT / BN);
+                const int k = k0 + bk0 + 4 * u;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) rb[u][e] = k + e < K ? *q[e] : 0;
             }
@@ -142,15 +145,18 @@ __device__ __forceinline__ void mfma_i32_tile(const MmArgs &a, const int row0, c
 #pragma unroll
             for (int p = 0; p < 4; ++p) *reinterpret_cast<uint32_t *>(as + p * BM * LD + rr * LD + 4 * kq) = w[p];
         }
+        static_assert(BQ == 2 || BQ == 4, "a B run of 8 or 16 bytes per plane");
+        typedef uint32_t brun __attribute__((ext_vector_type(BQ)));
+        brun wb[4];
 #pragma unroll
         for (int u = 0; u < BQ; ++u) {
-            const int f = tid + u * NT;
-            const int n = f % BN, kq = f / BN;
             uint32_t w[4];
             digit_planes(rb[u], w);
 #pragma unroll
-            for (int p = 0; p < 4; ++p) *reinterpret_cast<uint32_t *>(bs + p * BN * LD + n * LD + 4 * kq) = w[p];
+            for (int p = 0; p < 4; ++p) wb[p][u] = w[p];
         }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) *reinterpret_cast<brun *>(bs + p * BN * LD + (tid % BN) * LD + bk0) = wb[p];
     };
     auto compute = [&](int st) {
         const unsigned char *as = As0 + st * L::A + (wm * WTM + r) * LD + h * (BK / 2);
