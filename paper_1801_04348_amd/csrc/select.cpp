@@ -89,7 +89,10 @@ double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes
     const double imbalance = (double)(per_cu * ncu) / (double)tiles;
     const double resident = (double)std::min(bpc, per_cu);
     const double inflight = std::min(1.0, resident * inflight_bytes_per_tile / 65536.0);
-    const double seg = std::min(1.0, segment_bytes / 128.0);
+    // a wavefront's access is 64 lanes x 4 bytes: runs along a row shorter
+    // than 256 bytes split it over several rows (transposition of order 2^14:
+    // the 128-byte runs of 32-wide tiles 4.4 TB/s, the 256-byte ones 4.9)
+    const double seg = std::min(1.0, segment_bytes / 256.0);
     // one compute unit alone draws about 64 GB/s; all of them, 8 TB/s
     const double bw = std::min(8e12, 64e9 * (double)active) * 0.85 * std::max(inflight * seg, 1e-3);
     const double rounds = (double)((per_cu + bpc - 1) / bpc);

@@ -45,7 +45,8 @@ double tile_work_seconds(const pk_machine &m, const KernelEntry &e, int dtype, i
 // sustain -- the filled share of the last round of tiles, the bytes a compute
 // unit keeps in flight (about 64 KiB per compute unit covers HBM latency at
 // full bandwidth), and the narrowest contiguous segment a wavefront touches
-// (below 128 bytes a cache line is partly wasted) -- plus launch latency.
+// (below 256 bytes, one wavefront's 64 four-byte lanes, its access is split
+// over rows) -- plus launch latency.
 double streaming_seconds(const pk_machine &m, const KernelEntry &e, double bytes, int64_t tiles,
                          double inflight_bytes_per_tile, double segment_bytes);
 
